@@ -1,0 +1,593 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle (oracle/derive.py + oracle/hwenou_oracle.c)
+against something other than itself: the printed Appendix tables, the
+printed smoothness-indicator forms, the printed linear-scheme matrices and
+moment modification, the closed-form amplification matrix, exactness on
+polynomials, invariants and special cases.
+"""
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+from oracle import derive
+from oracle.driver import Problem
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    out = []
+    with open(os.path.join(GOLD, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                out.append(line.split())
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Appendix tables
+# ---------------------------------------------------------------------------
+
+def test_1d_reconstruction_matches_appendix():
+    r = derive.recon_1d()
+    derived = {f"c0_{l}": r["M0"][l] for l in range(5)}
+    derived.update({f"c1_{l}": r["M1"][l] for l in range(2)})
+    derived.update({f"c2_{l}": r["M2"][l] for l in range(2)})
+    rows = _rows("appendix_1d.txt")
+    assert len(rows) == 9
+    for name, *vals in rows:
+        assert [Fr(v) for v in vals] == list(derived[name]), name
+
+
+def test_2d_reconstruction_matches_appendix_up_to_one_sign():
+    r = derive.recon_2d()
+    derived = {f"c0_{n}": r["M0"][n] for n in range(15)}
+    for m in range(4):
+        for t in range(3):
+            derived[f"c{m + 1}_{t}"] = r["Mm"][m][t]
+    mismatches = []
+    for name, *vals in _rows("appendix_2d.txt"):
+        printed = [Fr(v) for v in vals]
+        for col, (a, b) in enumerate(zip(printed, derived[name])):
+            if a != b:
+                mismatches.append((name, col, a, b))
+    # the only difference: the u1 entry of c0_4 (printed +7/22, derived -7/22)
+    assert mismatches == [("c0_4", 0, Fr(7, 22), Fr(-7, 22))]
+
+
+def test_2d_xi_eta_coefficient_is_odd_under_x_reflection():
+    # Under x -> -x the stencil maps 1<->3, 4<->6, 7<->9, v -> -v, and the
+    # coefficient of xi*eta changes sign.  The derived row satisfies this; the
+    # printed one (with +7/22 on u1) does not.
+    col = {k: i for i, k in enumerate(derive.DATA_2D)}
+
+    def reflect(row):
+        out = [Fr(0)] * 17
+        lab_map = {1: 3, 2: 2, 3: 1, 4: 6, 5: 5, 6: 4, 7: 9, 8: 8, 9: 7}
+        for (kind, lab), i in col.items():
+            sgn = -1 if kind == "v" else 1
+            out[col[(kind, lab_map[lab])]] += sgn * row[i]
+        return out
+
+    derived = derive.recon_2d()["M0"][4]
+    assert reflect(derived) == [-v for v in derived]
+    printed = [Fr(v) for v in dict((r[0], r[1:]) for r in _rows("appendix_2d.txt"))["c0_4"]]
+    assert reflect(printed) != [-v for v in printed]
+
+
+def test_2d_p0_constraints_hold_exactly():
+    # p0 reproduces the 9 averages and v4, v6, w2, w8 for any data
+    r = derive.recon_2d()
+    M0 = r["M0"]
+    for kind, lab in [("u", k) for k in range(1, 10)] + [("v", 4), ("v", 6), ("w", 2), ("w", 8)]:
+        row = derive._cell_row_2d(kind, lab, derive.BASIS_2D)
+        # functional applied to p0 = row @ M0 must pick out exactly that datum
+        fun = [sum(row[n] * M0[n][j] for n in range(15)) for j in range(17)]
+        expect = [Fr(int(k == (kind, lab))) for k in derive.DATA_2D]
+        assert fun == expect
+
+
+# ---------------------------------------------------------------------------
+# smoothness indicators
+# ---------------------------------------------------------------------------
+
+def _gram_from_squares(dim, fix_1d_typo=False):
+    n = 5 if dim == 1 else 15
+    G = [[Fr(0)] * n for _ in range(n)]
+    for row in _rows("beta_printed.txt"):
+        if int(row[0]) != dim:
+            continue
+        wgt = Fr(row[1])
+        terms = {}
+        for t in row[3:]:
+            i, c = t.split(":")
+            terms[int(i)] = Fr(c)
+        if fix_1d_typo and dim == 1 and set(terms) == {1, 4}:
+            terms = {1: Fr(1), 3: Fr(1, 4)}
+        for a, ca in terms.items():
+            for b, cb in terms.items():
+                G[a][b] += wgt * ca * cb
+    return G
+
+
+def test_1d_beta_matches_corrected_printed_form():
+    G = derive.beta_gram_1d(4)
+    assert G == _gram_from_squares(1, fix_1d_typo=True)
+    # the form exactly as printed differs (its first square names c_{0,4})
+    assert G != _gram_from_squares(1, fix_1d_typo=False)
+    # expanded, as stated in the reading of the paper
+    assert G[1][1] == 1 and 2 * G[1][3] == Fr(1, 2) and G[2][2] == Fr(13, 3)
+    assert 2 * G[2][4] == Fr(21, 5) and G[3][3] == Fr(3129, 80)
+    assert G[4][4] == Fr(87617, 140)
+
+
+def test_2d_beta_matches_printed_form_exactly():
+    assert derive.beta_gram_2d(4) == _gram_from_squares(2)
+
+
+def test_linear_beta_is_sum_of_squared_slopes():
+    G = derive.beta_gram_2d(1)
+    assert G == [[0, 0, 0], [0, 1, 0], [0, 0, 1]]
+    assert derive.beta_gram_1d(1) == [[0, 0], [0, 1]]
+
+
+# ---------------------------------------------------------------------------
+# linear scheme (Section 2.3) through the oracle's C operator
+# ---------------------------------------------------------------------------
+
+def _linear_problem(n=12):
+    return Problem(1, "advection", n, (0.0, float(n)), weights="linear", adv=(1.0,))
+
+
+def _extract_linear_operator():
+    """Columns of the oracle's RHS and v^ for unit impulses; dx = 1."""
+    n = 12
+    P = _linear_problem(n)
+    j = 6
+    blocks = {}
+    vh = {}
+    for comp in (0, 1):
+        u = np.zeros((1, n))
+        m = np.zeros((1, 1, n))
+        (u if comp == 0 else m[0])[0, j] = 1.0
+        F1, Fm, mh = P.rhs(u, m, [1.0])
+        for name, off in (("A", 2), ("B", 1), ("C", 0), ("D", -1)):
+            i = j + off
+            blocks.setdefault(name, np.zeros((2, 2)))[:, comp] = [F1[0, i], Fm[0, 0, i]]
+        vh[comp] = {off: mh[0, 0, j + off] for off in (-2, -1, 0, 1, 2)}
+    return blocks, vh
+
+
+def test_linear_scheme_matrices_match_printed():
+    blocks, _ = _extract_linear_operator()
+    for name, *vals in _rows("linear_scheme.txt"):
+        if name in "ABCD" and len(name) == 1:
+            expect = np.array([float(Fr(v)) for v in vals]).reshape(2, 2)
+            np.testing.assert_allclose(blocks[name], expect, rtol=0, atol=1e-13)
+
+
+def test_moment_modification_matches_printed():
+    _, vh = _extract_linear_operator()
+    # impulse at cell j affects v^ of cell j+1 (as its u[i-1]/v[i-1]) and j-1
+    row = [r for r in _rows("linear_scheme.txt") if r[0] == "VHAT"][0][1:]
+    coef = {row[k]: float(Fr(row[k + 1])) for k in range(0, len(row), 2)}
+    np.testing.assert_allclose(vh[0][1], coef["u[i-1]"], atol=1e-14)
+    np.testing.assert_allclose(vh[0][-1], coef["u[i+1]"], atol=1e-14)
+    np.testing.assert_allclose(vh[1][1], coef["v[i-1]"], atol=1e-14)
+    np.testing.assert_allclose(vh[1][-1], coef["v[i+1]"], atol=1e-14)
+    for comp in (0, 1):
+        for off in (-2, 0, 2):
+            assert abs(vh[comp][off]) < 1e-14
+
+
+def _symbols(K, blocks=None):
+    """G~ and A^ of Section 2.3 from the printed matrices (or given blocks)."""
+    if blocks is None:
+        blocks = {r[0]: np.array([float(Fr(v)) for v in r[1:]]).reshape(2, 2)
+                  for r in _rows("linear_scheme.txt") if r[0] in ("A", "B", "C", "D")}
+    e = np.exp(1j * K)
+    Gt = blocks["A"] / e ** 2 + blocks["B"] / e + blocks["C"] + blocks["D"] * e
+    Ah = np.array([[1, 0], [5 / 76 * (e - 1 / e), -11 / 38 * (e + 1 / e)]])
+    return Gt, Ah
+
+
+def test_eigenvalues_of_symbol_match_printed_closed_form():
+    for K in (0.3, 1.1, 2.5, 4.0):
+        Gt, _ = _symbols(K)
+        e = np.exp(1j * K)
+        theta = (17161 * e ** 6 + 554226 * e ** 5 - 343029 * e ** 4 + 329356 * e ** 3
+                 - 71709 * e ** 2 + 29370 * e + 3025)
+        lam = [(267 + 131 * e + 267 / e + (55 + s * np.sqrt(theta)) / e ** 2) / 456
+               for s in (1, -1)]
+        ev = np.linalg.eigvals(Gt)
+        for l in lam:
+            assert np.min(np.abs(ev - l)) < 1e-12
+
+
+def _max_radius(lmbda, modified=True, nK=2000):
+    rmax = 0.0
+    for K in np.linspace(0, 2 * np.pi, nK, endpoint=False):
+        Gt, Ah = _symbols(K)
+        if not modified:
+            Ah = np.eye(2)
+        G1 = Ah + lmbda * Gt
+        G3 = Ah / 3 + 0.5 * G1 @ Ah + G1 @ G1 @ G1 / 6
+        rmax = max(rmax, np.max(np.abs(np.linalg.eigvals(G3))))
+    return rmax
+
+
+def test_stability_bound_of_modified_rk3():
+    bound = float([r for r in _rows("linear_scheme.txt") if r[0] == "CFL"][0][1])
+    assert _max_radius(bound - 0.005) <= 1 + 1e-10
+    assert _max_radius(bound + 0.01) > 1 + 1e-4
+    # Theorem 1: without the moment modification the scheme is unstable
+    assert _max_radius(0.01, modified=False, nK=400) > 1.01
+    assert _max_radius(0.1, modified=False, nK=400) > 1.3
+
+
+def test_oracle_full_step_equals_amplification_matrix():
+    """Linear weights, a = 1, periodic: n oracle RK steps on a Fourier mode
+    equal G3^n from the printed matrices (closed form, Theorem 2)."""
+    n = 16
+    P = Problem(1, "advection", n, (0.0, 2.0), weights="linear", adv=(1.0,))
+    dx = 2.0 / n
+    lam = 0.5
+    dt = lam * dx
+    k = 3  # mode e^{i k 2 pi x/L}, K = k * 2 pi / n
+    K = 2 * np.pi * k / n
+    rng = np.random.default_rng(7)
+    amp = rng.normal(size=2) + 1j * rng.normal(size=2)
+    ii = np.arange(n)
+    mode = np.exp(1j * K * ii)
+    u0 = np.real(amp[0] * mode)[None]
+    v0 = np.real(amp[1] * mode)[None, None]
+    u, m = u0, v0
+    steps = 7
+    for _ in range(steps):
+        u, m = P.step(u, m, dt, [1.0])
+    Gt, Ah = _symbols(K)
+    G1 = Ah + lam * Gt
+    G3 = Ah / 3 + 0.5 * G1 @ Ah + G1 @ G1 @ G1 / 6
+    a = np.linalg.matrix_power(G3, steps) @ amp
+    np.testing.assert_allclose(u[0], np.real(a[0] * mode), atol=1e-13)
+    np.testing.assert_allclose(m[0, 0], np.real(a[1] * mode), atol=1e-13)
+
+
+def test_linear_advection_error_matches_amplification_closed_form():
+    """The sine-advection workload (N = 200, CFL 0.2, T = 2) with linear
+    weights: the L-infinity error of the oracle equals that of G3^1000 applied
+    to the exact moments of the mode (computed from the printed matrices)."""
+    n = 200
+    P = Problem(1, "advection", n, (0.0, 2.0), weights="linear", adv=(1.0,))
+    u0, m0 = W.advection_sine_1d(n)
+    u, m, t, steps = P.advance(u0, m0, cfl=0.2, t_final=2.0, alpha=[1.0])
+    assert steps == 1000 and abs(t - 2.0) < 1e-13
+    err = np.abs(u - u0).max()
+    K = 2 * np.pi / n
+    Gt, Ah = _symbols(K)
+    G1 = Ah + 0.2 * Gt
+    G3 = Ah / 3 + 0.5 * G1 @ Ah + G1 @ G1 @ G1 / 6
+    # complex amplitudes of the single Fourier mode: u_i = Re(a_u e^{i K i})
+    ii = np.arange(n)
+    z = np.exp(1j * K * ii)
+    a_u = np.sum(u0[0] * np.conj(z)) * 2 / n
+    a_v = np.sum(m0[0, 0] * np.conj(z)) * 2 / n
+    np.testing.assert_allclose(np.real(a_u * z), u0[0], atol=1e-14)
+    a = np.linalg.matrix_power(G3, steps) @ np.array([a_u, a_v])
+    expect = np.abs(np.real(a[0] * z) - u0[0]).max()
+    assert abs(err - expect) < 1e-11  # round-off of O(1) values over 1000 steps
+    assert abs(err - 6.53e-8) < 0.01e-8
+
+
+# ---------------------------------------------------------------------------
+# polynomial exactness (linear weights), brute force on tiny grids
+# ---------------------------------------------------------------------------
+
+def _poly1d_moments(coef, n, a, b):
+    return W.cell_moments_1d(lambda x: np.polyval(coef[::-1], x), a, b, n, q=6)
+
+
+def test_1d_exact_on_quartics():
+    rng = np.random.default_rng(11)
+    n, a, b = 9, 0.0, 1.8
+    dx = (b - a) / n
+    for trial in range(3):
+        coef = rng.normal(size=5)
+        f = lambda x: np.polyval(coef[::-1], x)
+        ub, vb = _poly1d_moments(coef, n, a, b)
+        P = Problem(1, "burgers", n, (a, b), bc="transmissive", weights="linear")
+        F1, Fm, mh = P.rhs(ub, vb, [0.7])
+        xl = a + np.arange(n) * dx
+        nodes = np.array([-0.5, -np.sqrt(5) / 10, np.sqrt(5) / 10, 0.5])
+        wts = np.array([1, 5, 5, 1]) / 12
+        fl = 0.5 * f(xl) ** 2
+        fr = 0.5 * f(xl + dx) ** 2
+        vol = sum(w * 0.5 * f(xl + dx * (0.5 + s)) ** 2 for s, w in zip(nodes, wts))
+        e1 = -(fr - fl) / dx
+        e2 = -(fl + fr) / (2 * dx) + vol / dx
+        inner = slice(2, n - 2)
+        np.testing.assert_allclose(F1[0, inner], e1[inner], rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(Fm[0, 0, inner], e2[inner], rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(mh[0, 0, inner], vb[0, 0, inner], rtol=1e-11, atol=1e-12)
+
+
+def test_2d_exact_on_quartics():
+    rng = np.random.default_rng(12)
+    n, L = 7, 1.4
+    dx = L / n
+    basis = derive.BASIS_2D
+    for trial in range(2):
+        coef = rng.normal(size=15)
+        f = lambda X, Y: sum(c * X ** p * Y ** q for c, (p, q) in zip(coef, basis))
+        ub, mom = W.cell_moments_2d(f, (0, L, 0, L), n, n, q=4)
+        P = Problem(2, "burgers", (n, n), (0, L, 0, L), bc="transmissive", weights="linear")
+        F1, Fm, mh = P.rhs(ub, mom, [0.6, 0.9])
+        g = np.array([-np.sqrt(15) / 10, 0.0, np.sqrt(15) / 10])
+        gw = np.array([5, 8, 5]) / 18
+        xl = np.arange(n) * dx
+        XL, YL = np.meshgrid(xl, xl)  # [j, i]
+        h = lambda X, Y: 0.5 * f(X, Y) ** 2
+        fl = sum(w * h(XL, YL + dx * (0.5 + s)) for s, w in zip(g, gw))
+        fr = sum(w * h(XL + dx, YL + dx * (0.5 + s)) for s, w in zip(g, gw))
+        gb = sum(w * h(XL + dx * (0.5 + s), YL) for s, w in zip(g, gw))
+        gt = sum(w * h(XL + dx * (0.5 + s), YL + dx) for s, w in zip(g, gw))
+        fm = sum(w * s * h(XL, YL + dx * (0.5 + s)) for s, w in zip(g, gw))
+        fp = sum(w * s * h(XL + dx, YL + dx * (0.5 + s)) for s, w in zip(g, gw))
+        gmb = sum(w * s * h(XL + dx * (0.5 + s), YL) for s, w in zip(g, gw))
+        gmt = sum(w * s * h(XL + dx * (0.5 + s), YL + dx) for s, w in zip(g, gw))
+        vol = sum(wa * wb * h(XL + dx * (0.5 + sa), YL + dx * (0.5 + sb))
+                  for sa, wa in zip(g, gw) for sb, wb in zip(g, gw))
+        e1 = -(fr - fl) / dx - (gt - gb) / dx
+        e2 = -(fl + fr) / (2 * dx) + vol / dx - (gmt - gmb) / dx
+        e3 = -(fp - fm) / dx - (gb + gt) / (2 * dx) + vol / dx
+        s = (slice(2, n - 2), slice(2, n - 2))
+        np.testing.assert_allclose(F1[0][s], e1[s], rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(Fm[0, 0][s], e2[s], rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(Fm[1, 0][s], e3[s], rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(mh[0, 0][s], mom[0, 0][s], rtol=1e-10, atol=1e-11)
+        np.testing.assert_allclose(mh[1, 0][s], mom[1, 0][s], rtol=1e-10, atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# nonlinear weights: special cases
+# ---------------------------------------------------------------------------
+
+def test_zero_averages_give_linear_weights():
+    """u_{i-1} = u_i = u_{i+1} = 0 makes u_ave = 0 and the weights linear
+    (Remark after Eq. (2.8)): the same output as the linear-weight oracle."""
+    n = 10
+    rng = np.random.default_rng(3)
+    u = np.zeros((1, n))
+    v = rng.normal(size=(1, 1, n)) * 1e-2
+    P = Problem(1, "advection", n, (0, 1), adv=(1.0,))
+    Pl = Problem(1, "advection", n, (0, 1), adv=(1.0,), weights="linear")
+    a = P.rhs(u, v, [1.0])
+    b = Pl.rhs(u, v, [1.0])
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x, y, rtol=1e-14, atol=1e-16)
+
+
+def test_smooth_data_weights_close_to_linear():
+    # tau = 0 (quadratic data with beta_0 = beta_1 = beta_2 in 1D is rare);
+    # constant data has beta = 0 everywhere, tau = 0, weights linear
+    n = 8
+    P = Problem(1, "advection", n, (0, 1), adv=(1.0,))
+    u = np.full((1, n), 2.5)
+    v = np.zeros((1, 1, n))
+    F1, Fm, mh = P.rhs(u, v, [1.0])
+    assert np.abs(F1).max() == 0.0 and np.abs(mh).max() == 0.0
+    np.testing.assert_allclose(Fm, 0.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("zeta", [2.0 ** -20, 2.0 ** 14])
+def test_scale_invariance_is_exact_with_zero_epsilon(zeta):
+    n = 24
+    u, v = W.euler_1d_shocktube(n, seed=9)
+    u, v = u[:1], v[:, :1]  # density only, as a scalar field
+    # periodic: a transmissive ghost copy makes beta_1 = 0, undefined when eps = 0
+    P = Problem(1, "advection", n, (0, 1), adv=(1.0,), eps=0.0)
+    a = P.rhs(u, v, [1.0])
+    assert all(np.isfinite(x).all() for x in a)
+    b = P.rhs(zeta * u, zeta * v, [1.0])
+    for x, y in zip(a, b):
+        assert np.array_equal(zeta * x, y)
+    # negative control: the scale-dependent weights (u_ave = 1) differ
+    Pz = Problem(1, "advection", n, (0, 1), adv=(1.0,), eps=0.0, weights="zq")
+    a = Pz.rhs(u, v, [1.0])
+    b = Pz.rhs(zeta * u, zeta * v, [1.0])
+    assert np.abs(zeta * a[0] - b[0]).max() > 1e-6 * np.abs(b[0]).max()
+
+
+def test_scale_invariance_2d_euler_with_zero_epsilon():
+    n = 10
+    u, m = W.euler_2d_vortex_quadrant(n, seed=5, q=2)
+    P = Problem(2, "euler", (n, n), (0, 10, 0, 10), eps=0.0)
+    zeta = 2.0 ** 10
+    # scale rho, momentum and energy alike (velocities unchanged, p scaled)
+    a = P.rhs(u, m, [1.3, 1.7])
+    b = P.rhs(zeta * u, zeta * m, [1.3, 1.7])
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(zeta * x, y, rtol=1e-12, atol=1e-12 * np.abs(y).max())
+
+
+# ---------------------------------------------------------------------------
+# invariants
+# ---------------------------------------------------------------------------
+
+def test_conservation_1d_euler_periodic():
+    n = 64
+    u, m = W.random_smooth_1d(n, 3, seed=21, positive_euler=True)
+    P = Problem(1, "euler", n, (0, 2))
+    u1, m1, t, s = P.advance(u, m, cfl=0.6, max_steps=20)
+    drift = np.abs(u1.sum(axis=1) - u.sum(axis=1))
+    assert np.all(drift <= 1e-12 * np.abs(u).sum(axis=1))
+
+
+def test_conservation_2d_euler_periodic():
+    n = 16
+    u, m = W.euler_2d_vortex_quadrant(n, seed=22, q=2)
+    P = Problem(2, "euler", (n, n), (0, 10, 0, 10))
+    u1, m1, t, s = P.advance(u, m, cfl=0.6, max_steps=5)
+    drift = np.abs(u1.sum(axis=(1, 2)) - u.sum(axis=(1, 2)))
+    assert np.all(drift <= 1e-12 * np.abs(u).sum(axis=(1, 2)))
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_constant_state_preserved(dim):
+    if dim == 1:
+        P = Problem(1, "euler", 20, (0, 1), bc="transmissive")
+        u = np.array([1.3, 0.4, 2.9])[:, None] * np.ones((3, 20))
+        m = np.zeros((1, 3, 20))
+    else:
+        P = Problem(2, "euler", (8, 10), (0, 1, 0, 1.25), bc=("periodic", "periodic",
+                                                                "transmissive", "transmissive"))
+        u = np.array([0.7, 0.1, -0.3, 2.1])[:, None, None] * np.ones((4, 10, 8))
+        m = np.zeros((2, 4, 10, 8))
+    u1, m1, _, _ = P.advance(u, m, cfl=0.6, max_steps=10)
+    np.testing.assert_allclose(u1, u, rtol=1e-14)
+    assert np.abs(m1).max() < 1e-14
+
+
+def test_mirror_symmetry_1d_euler():
+    n = 30
+    u, m = W.euler_1d_shocktube(n, seed=31)
+    P = Problem(1, "euler", n, (0, 1), bc="transmissive")
+    sgn_u = np.array([1, -1, 1])[:, None]
+    um = (u * sgn_u)[:, ::-1].copy()
+    mm = (-m * sgn_u[None])[:, :, ::-1].copy()
+    al = P.max_wavespeed(u)
+    F1, Fm, mh = P.rhs(u, m, al)
+    G1, Gm, gh = P.rhs(um, mm, al)
+    np.testing.assert_allclose(G1, (F1 * sgn_u)[:, ::-1], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(Gm, (-Fm * sgn_u[None])[:, :, ::-1], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(gh, (-mh * sgn_u[None])[:, :, ::-1], rtol=1e-12, atol=1e-12)
+
+
+def test_transpose_symmetry_2d_euler():
+    n = 10
+    u, m = W.euler_2d_vortex_quadrant(n, seed=32, q=2)
+    P = Problem(2, "euler", (n, n), (0, 10, 0, 10))
+    perm = [0, 2, 1, 3]  # swap momenta
+    ut = u[perm].transpose(0, 2, 1).copy()
+    mt = m[::-1][:, perm].transpose(0, 1, 3, 2).copy()
+    al = P.max_wavespeed(u)
+    F1, Fm, mh = P.rhs(u, m, al)
+    G1, Gm, gh = P.rhs(ut, mt, al[::-1].copy())
+    np.testing.assert_allclose(G1, F1[perm].transpose(0, 2, 1), rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(Gm, Fm[::-1][:, perm].transpose(0, 1, 3, 2), rtol=1e-11,
+                               atol=1e-11)
+    np.testing.assert_allclose(gh, mh[::-1][:, perm].transpose(0, 1, 3, 2), rtol=1e-11,
+                               atol=1e-11)
+
+
+def test_2d_reduces_to_1d_for_y_constant_data():
+    n = 16
+    u1, v1 = W.random_smooth_1d(n, 1, seed=41)
+    P1 = Problem(1, "advection", n, (0, 2), adv=(1.0,), weights="linear")
+    P2 = Problem(2, "advection", (n, 6), (0, 2, 0, 0.75), adv=(1.0, 0.5), weights="linear")
+    u2 = np.repeat(u1[:, None, :], 6, axis=1)
+    m2 = np.zeros((2, 1, 6, n))
+    m2[0] = np.repeat(v1[0][:, None, :], 6, axis=1)
+    a = P1.advance(u1, v1, cfl=0.4, max_steps=6, alpha=[1.0])
+    b = P2.advance(u2, m2, fixed_dt=0.4 * 2 / n, max_steps=6, alpha=[1.0, 0.5])
+    a = P1.advance(u1, v1, fixed_dt=0.4 * 2 / n, max_steps=6, alpha=[1.0])
+    np.testing.assert_allclose(b[0][0], np.repeat(a[0][0][None], 6, axis=0), atol=1e-13)
+    np.testing.assert_allclose(b[1][0, 0], np.repeat(a[1][0, 0][None], 6, axis=0), atol=1e-13)
+    assert np.abs(b[1][1]).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# accuracy (Section 3.1): orders and magnitudes
+# ---------------------------------------------------------------------------
+
+def _table(example):
+    return {int(r[1]): (float(r[2]), float(r[3])) for r in _rows("accuracy_tables.txt")
+            if r[0] == example}
+
+
+def test_1d_euler_accuracy_matches_paper_table():
+    tab = _table("euler1d")
+    errs = {}
+    for n in (80, 160):
+        P = Problem(1, "euler", n, (0, 2))
+        u0, m0 = W.euler_1d_sine(n)
+        ue, _ = W.euler_1d_sine(n, t=2.0)
+        u, m, t, s = P.advance(u0, m0, cfl=0.6, t_final=2.0, h_power=5.0 / 3.0)
+        e = np.abs(u[0] - ue[0])
+        errs[n] = (e.max(), e.mean())
+        # magnitudes within a factor 3 of the printed table (dt is unstated)
+        assert tab[n][0] / 3 < errs[n][0] < 3 * tab[n][0]
+        assert tab[n][1] / 3 < errs[n][1] < 3 * tab[n][1]
+    order = np.log2(errs[80][1] / errs[160][1])
+    assert order > 4.8
+
+
+def test_1d_burgers_accuracy_matches_paper_table():
+    tab = _table("burgers1d")
+    tabv = _table("burgers1d_v")
+    T = 0.5 / np.pi
+    errs = {}
+    for n in (80, 160):
+        P = Problem(1, "burgers", n, (0, 2))
+        u0, m0 = W.burgers_1d_initial(n)
+        ue, ve = W.burgers_1d_exact_moments(n, T)
+        u, m, t, s = P.advance(u0, m0, cfl=0.6, t_final=T, h_power=5.0 / 3.0)
+        e = np.abs(u[0] - ue[0])
+        ev = np.abs(m[0, 0] - ve[0, 0])
+        errs[n] = e.mean()
+        assert tab[n][0] / 3 < e.max() < 3 * tab[n][0]
+        assert tab[n][1] / 3 < e.mean() < 3 * tab[n][1]
+        assert tabv[n][1] / 3 < ev.mean() < 3 * tabv[n][1]
+    assert np.log2(errs[80] / errs[160]) > 4.8
+
+
+@pytest.mark.slow
+def test_2d_orders_short_time():
+    T = 0.2
+    errs = {}
+    for n in (20, 40):
+        P = Problem(2, "euler", (n, n), (0, 4, 0, 4))
+        u0, m0 = W.euler_2d_sine(n)
+        ue, _ = W.euler_2d_sine(n, t=T)
+        u, m, t, s = P.advance(u0, m0, cfl=0.6, t_final=T, h_power=5.0 / 3.0)
+        errs[n] = np.abs(u[0] - ue[0]).mean()
+    assert np.log2(errs[20] / errs[40]) > 4.0
+    errs = {}
+    for n in (20, 40):
+        P = Problem(2, "burgers", (n, n), (0, 4, 0, 4))
+        u0, m0 = W.burgers_2d_initial(n)
+        ue, _ = W.burgers_2d_exact_moments(n, T)
+        u, m, t, s = P.advance(u0, m0, cfl=0.6, t_final=T, h_power=5.0 / 3.0)
+        errs[n] = np.abs(u[0] - ue[0]).mean()
+    assert np.log2(errs[20] / errs[40]) > 4.5
+
+
+def test_theorem1_unmodified_scheme_blows_up():
+    """Using v instead of v^ in the Runge-Kutta bases (the unmodified SSP-RK3
+    of Theorem 1) is unstable even at CFL 0.1; the modified scheme is not."""
+    n = 32
+    P = Problem(1, "advection", n, (0, 2), adv=(1.0,), weights="linear")
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=(1, n))
+    v = rng.normal(size=(1, 1, n)) * 0.1
+    dt = 0.1 * 2 / n
+
+    def unmodified_step(u, v):
+        F1, Fm, _ = P.rhs(u, v, [1.0])
+        u1, v1 = u + dt * F1, v + dt * Fm
+        F1, Fm, _ = P.rhs(u1, v1, [1.0])
+        u2, v2 = 0.75 * u + 0.25 * (u1 + dt * F1), 0.75 * v + 0.25 * (v1 + dt * Fm)
+        F1, Fm, _ = P.rhs(u2, v2, [1.0])
+        return u / 3 + 2 / 3 * (u2 + dt * F1), v / 3 + 2 / 3 * (v2 + dt * Fm)
+
+    a, b = u, v
+    for _ in range(200):
+        a, b = unmodified_step(a, b)
+    assert np.abs(a).max() > 1e3 * np.abs(u).max()
+    c, d, _, _ = P.advance(u, v, fixed_dt=dt, max_steps=200, alpha=[1.0])
+    assert np.abs(c).max() < 2 * np.abs(u).max()
