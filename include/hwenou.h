@@ -1,0 +1,151 @@
+/*
+ * hwenou.h -- C-ABI of the MI355X HWENO-U library (libhwenou.so).
+ *
+ * The library advances the zeroth- and first-order moments of hyperbolic
+ * conservation laws with the fifth-order moment-based Hermite WENO scheme
+ * with unified stencils (HWENO-U) of Fan, Qiu & Zhao, arXiv 2402.03074:
+ *   - problem statement: Section 2.1 (1D: u_t + f(u)_x = 0 on a uniform grid
+ *     of [a, b], cell averages u_i and first-order moments v_i) and
+ *     Section 2.2 (2D: u_t + f(u)_x + g(u)_y = 0 on [a, b] x [c, d], moments
+ *     u_ij, v_ij, w_ij);
+ *   - spatial operator: Steps 1-3 of Sections 2.1 / 2.2 (reconstruction,
+ *     smoothness indicators, scale-invariant nonlinear weights, moment
+ *     modification) and the semi-discrete schemes Eq. (2.4) / (2.18) with
+ *     Lax-Friedrichs fluxes;
+ *   - time discretisation: the modified SSP-RK3 of Eq. (2.11) (Step 4), which
+ *     uses the modified moments v^ (w^) in the Runge-Kutta bases;
+ *   - Euler equations: local characteristic decomposition (Remark 2.1).
+ *
+ * Memory model.  All state arrays are device memory owned by the caller.
+ * Several independent instances may share one handle; instance k occupies
+ * cells [offset_k, offset_k + nx_k * ny_k) of every component plane, with x
+ * the fastest index.  With P = the plane length (max over k of
+ * offset_k + nx_k * ny_k):
+ *   ubar : double [ncomp][P]                  cell averages
+ *   mom  : T      [dim][ncomp][P]              first-order moments, d = 0 the
+ *                                              x-moment v, d = 1 the y-moment w
+ * T is double for HWENOU_FP64 and float for HWENOU_MIXED.  ncomp is 1 for
+ * scalar laws, 3 (1D) or 4 (2D) for Euler (rho, rho u[, rho v], E).
+ * Device arrays alpha [n_inst][2] (wave speeds in x and y) and dt [n_inst]
+ * are doubles.  Pointers must be aligned to their element size.
+ *
+ * Every call is asynchronous on the handle's stream unless stated.  A handle
+ * is not thread-safe.  Return values are HWENOU_OK or an error code below;
+ * hwenou_strerror() describes a code (for HWENOU_EHIP, the last HIP error
+ * text of the calling thread).
+ */
+#ifndef HWENOU_H
+#define HWENOU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HWENOU_OK = 0,
+  HWENOU_EINVAL = 1,        /* bad argument: enum, size, pointer alignment, order of calls */
+  HWENOU_ENOMEM = 2,        /* device allocation failed */
+  HWENOU_EHIP = 3,          /* a HIP call failed */
+  HWENOU_ENONPHYSICAL = 4,  /* rho <= 0, p <= 0 or non-finite value after a stage */
+  HWENOU_EUNSUPPORTED = 5
+};
+
+enum { HWENOU_EQ_ADVECTION = 0, HWENOU_EQ_BURGERS = 1, HWENOU_EQ_EULER = 2 };
+enum { HWENOU_FP64 = 0, HWENOU_MIXED = 1 };
+/* nonlinear weights: scale-invariant (Eq. (2.8)/(2.14)), the scale-dependent
+ * original (u_ave = 1, Remark 2.1 of Section 2.1), or linear (w = gamma). */
+enum { HWENOU_W_SCALE_INVARIANT = 0, HWENOU_W_ZQ = 1, HWENOU_W_LINEAR = 2 };
+enum { HWENOU_BC_PERIODIC = 0, HWENOU_BC_TRANSMISSIVE = 1 };
+
+/* Scheme description. */
+typedef struct hwenou_desc {
+  int dim;          /* 1 or 2 */
+  int eq;           /* HWENOU_EQ_*; advection: f = adv[0] u, g = adv[1] u;
+                       Burgers: f = g = u^2/2; Euler: ideal gas */
+  int precision;    /* HWENOU_FP64 or HWENOU_MIXED (FP64 averages, smoothness
+                       indicators and weights; FP32 moments, point values, fluxes) */
+  int char_decomp;  /* Euler: 1 = local characteristic variables, 0 = conserved */
+  int weights;      /* HWENOU_W_* */
+  double adv[2];    /* advection velocity */
+  double gas_gamma; /* ratio of specific heats (Euler) */
+  double gamma_low; /* linear weight of every linear polynomial (paper: 1/400) */
+  double eps;       /* epsilon of the nonlinear weights (paper: 1e-10) */
+} hwenou_desc;
+
+/* One instance: a uniform grid of nx x ny cells on [x0, x1] x [y0, y1]
+ * (ny = 1, y0/y1 ignored in 1D).  bc: x-lo, x-hi, y-lo, y-hi.  Transmissive
+ * ghost cells copy the average and moments of the boundary cell. */
+typedef struct hwenou_inst {
+  int nx, ny;
+  double x0, x1, y0, y1;
+  int bc[4];
+  int64_t offset;
+} hwenou_inst;
+
+typedef struct hwenou_handle hwenou_handle;
+
+/* Create a handle for n_inst instances sharing one scheme description.
+ * `stream` is a hipStream_t (NULL = the default stream); every later call is
+ * ordered on it.  The handle owns its scratch: the stage buffers used by
+ * hwenou_advance, the stored modified moments of stage 0, per-instance
+ * alpha/dt/t/step arrays and the work lists.  Errors: EINVAL (dim, eq,
+ * precision or weights out of range; n_inst < 1; nx or ny < 3; overlapping
+ * instances; gas_gamma <= 1 for Euler), ENOMEM, EHIP.  On error *out is NULL. */
+int hwenou_create(const hwenou_desc* desc, int n_inst, const hwenou_inst* inst, void* stream,
+                  hwenou_handle** out);
+
+/* Release the handle and its device memory (synchronises its stream). */
+int hwenou_destroy(hwenou_handle* h);
+
+/* Static description of an error code. */
+const char* hwenou_strerror(int code);
+
+/* alpha_dev[k][d] = max over the cells of instance k of |f_d'(u)| at the
+ * cell averages (Euler: |u_d| + c), d < dim; the Lax-Friedrichs coefficient
+ * of Section 2.1 and the CFL wave speed.  Asynchronous.  A non-physical
+ * average is reported by the next hwenou_advance or hwenou_status call. */
+int hwenou_max_wavespeed(hwenou_handle* h, const double* ubar, double* alpha_dev);
+
+/* One fused stage s in {0, 1, 2} of the modified SSP-RK3 (Eq. (2.11)):
+ *   s = 0: out = (u, v^) + dt F(in)                 with (u, v^) from `in`
+ *   s = 1: out = 3/4 (u^n, v^n) + 1/4 ((u, v^) + dt F(in))
+ *   s = 2: out = 1/3 (u^n, v^n) + 2/3 ((u, v^) + dt F(in))
+ * where v^ (and w^) are the HWENO moment modifications of `in` and
+ * (u^n, v^n) is the base of the step: stage 0 records ubar_in as u^n (it must
+ * stay valid and unchanged until stage 2 has run, except that stage 2 may
+ * write its output into it) and stores v^n in the handle.  dt_dev [n_inst]
+ * and alpha_dev [n_inst][2] are device arrays.  `in` and `out` must not
+ * alias.  Asynchronous.  Errors: EINVAL (s out of range, stage 1/2 before
+ * stage 0, misaligned pointer), EHIP. */
+int hwenou_stage(hwenou_handle* h, int s, const double* dt_dev, const double* alpha_dev,
+                 const double* ubar_in, const void* mom_in, double* ubar_out, void* mom_out);
+
+/* Advance every instance in place until t_final or max_steps steps.  Each
+ * step takes alpha from the cell averages of U^n, dt = min(CFL dx / alpha,
+ * t_final - t) (1D) or CFL / (alpha_1/dx + alpha_2/dy) clipped likewise (2D),
+ * and runs the three stages; whole steps are replayed from a captured HIP
+ * graph with dt on the device.  Synchronises once at the end (plus one small
+ * read-back per 32 steps to stop early).  t_out [n_inst] and steps_out
+ * [n_inst] are host arrays (may be NULL).  Errors: EINVAL (cfl <= 0,
+ * t_final < 0, max_steps < 0), ENONPHYSICAL (some instance left the
+ * physical states; the arrays hold the last step), EHIP. */
+int hwenou_advance(hwenou_handle* h, double* ubar, void* mom, double cfl, double t_final,
+                   int max_steps, double* t_out, int* steps_out);
+
+/* Read and clear the handle's status flag (synchronous): HWENOU_OK or
+ * HWENOU_ENONPHYSICAL. */
+int hwenou_status(hwenou_handle* h);
+
+/* Launch configuration of the stage kernels: waves per compute unit of the
+ * persistent launch (1..32) and, in 2D, the rows a wave marches per work
+ * item before the work list splits (0 = balanced automatically).  Used by
+ * the autotuner; takes effect on the next call. */
+int hwenou_set_launch(hwenou_handle* h, int waves_per_cu, int rows_per_item);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HWENOU_H */

@@ -1,0 +1,123 @@
+// Auxiliary kernels of the time loop: the maximum wave speed
+// alpha = max |f'(u)| over the cell averages (Section 2.1, used by the
+// Lax-Friedrichs flux and the CFL condition), the per-instance time step
+// dt = min(CFL dx / alpha, T - t) in 1D and CFL / (alpha_1/dx + alpha_2/dy)
+// in 2D, and the per-step bookkeeping of t, the step count and completion.
+// All per-instance state lives on the device so that whole steps can be
+// replayed from a captured graph without host synchronisation.
+#include "hwenou_internal.hpp"
+
+namespace hwenou {
+
+template <int EQ, int NC>
+__global__ __launch_bounds__(256) void max_wavespeed_kernel(const AuxArgs A) {
+  const int inst = blockIdx.y;
+  const InstDev I = A.inst[inst];
+  const long long n = (long long)I.nx * I.ny;
+  double mx = 0.0, my = 0.0;
+  bool ok = true;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    double U[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) U[k] = A.u[k * A.plane + I.offset + c];
+    double sx, sy;
+    ok = wave_speeds<EQ, NC>(A.P, U, sx, sy) && ok;
+    mx = fmax(mx, sx);
+    my = fmax(my, sy);
+  }
+  if (!ok) atomicOr(A.status, 1);
+  mx = wave_max(mx);
+  my = wave_max(my);
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_nonneg(&A.alpha[2 * inst], mx);
+    atomic_max_nonneg(&A.alpha[2 * inst + 1], my);
+  }
+}
+
+__global__ void zero_alpha_kernel(double* alpha, int n) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    alpha[k] = 0.0;
+}
+
+hipError_t launch_max_wavespeed(const AuxArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(zero_alpha_kernel, dim3(1), dim3(256), 0, s, a.alpha, 2 * a.n_inst);
+  // 64 blocks per instance, grid-stride over its cells
+  const dim3 grid(64, a.n_inst);
+  if (a.eq == EQ_ADVECTION)
+    hipLaunchKernelGGL((max_wavespeed_kernel<EQ_ADVECTION, 1>), grid, dim3(256), 0, s, a);
+  else if (a.eq == EQ_BURGERS)
+    hipLaunchKernelGGL((max_wavespeed_kernel<EQ_BURGERS, 1>), grid, dim3(256), 0, s, a);
+  else if (a.dim == 1)
+    hipLaunchKernelGGL((max_wavespeed_kernel<EQ_EULER, 3>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((max_wavespeed_kernel<EQ_EULER, 4>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Start of a step: time step per instance, completion test, and the reset of
+// the wave-speed accumulator the last stage fills.
+__global__ __launch_bounds__(256) void dt_kernel(const AuxArgs A) {
+  for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) {
+    const InstDev I = A.inst[k];
+    A.alpha_next[2 * k] = 0.0;
+    A.alpha_next[2 * k + 1] = 0.0;
+    const double t = A.t[k];
+    const bool finished = A.done[k] || A.steps[k] >= A.max_steps ||
+                          t >= A.t_final * (1.0 - 1e-14);
+    if (finished) {
+      A.done[k] = 1;
+      A.dt[k] = 0.0;
+      continue;
+    }
+    double dt;
+    if (A.dim == 1)
+      dt = A.cfl * I.dx / A.alpha[2 * k];
+    else
+      dt = A.cfl / (A.alpha[2 * k] / I.dx + A.alpha[2 * k + 1] / I.dy);
+    if (!(dt > 0.0) || !isfinite(dt)) {  // zero or non-finite wave speed
+      A.done[k] = 1;
+      A.dt[k] = 0.0;
+      atomicOr(A.status, 2);
+      continue;
+    }
+    if (t + dt > A.t_final) dt = A.t_final - t;
+    A.dt[k] = dt;
+  }
+}
+
+// End of a step: advance t and the step count, take the new wave speed, and
+// count the instances still running.
+__global__ __launch_bounds__(256) void finish_kernel(const AuxArgs A) {
+  __shared__ int running;
+  if (threadIdx.x == 0) running = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) {
+    if (A.done[k]) continue;
+    A.t[k] += A.dt[k];
+    A.steps[k] += 1;
+    A.alpha[2 * k] = A.alpha_next[2 * k];
+    A.alpha[2 * k + 1] = A.alpha_next[2 * k + 1];
+    const bool finished = A.steps[k] >= A.max_steps || A.t[k] >= A.t_final * (1.0 - 1e-14);
+    if (finished)
+      A.done[k] = 1;
+    else
+      mine = 1;
+  }
+  if (mine) atomicOr(&running, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) A.all_done[0] = running ? 0 : 1;
+}
+
+hipError_t launch_dt(const AuxArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const AuxArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace hwenou

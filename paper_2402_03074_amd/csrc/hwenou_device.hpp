@@ -1,0 +1,409 @@
+// Device-side building blocks of the HWENO-U stage operator for gfx950.
+//
+// Everything here follows Section 2 of Fan, Qiu & Zhao, "A moment-based
+// Hermite WENO scheme with unified stencils for hyperbolic conservation
+// laws" (arXiv 2402.03074):
+//   * reconstruction coefficients of p0 (quartic) and p_m (linear): the
+//     Appendix tables, with the 2D c_{0,4} u_1 entry taken as -7/22 (the
+//     value the moment conditions give; the printed +7/22 breaks the
+//     antisymmetry of the xi*eta coefficient under x -> -x);
+//   * smoothness indicators: Eq. (2.7) in 1D with the first square read as
+//     (c_{0,1} + c_{0,3}/4)^2, and the printed sum of squares of Eq. (2.12) in 2D;
+//   * scale-invariant nonlinear weights, Eq. (2.8) / (2.14);
+//   * reconstruction u_i(x) and the HWENO moment modification, Eq. (2.10) / (2.15),
+//     written as one combined polynomial C = (w0/g0) p0 + sum_m (w_m - w0 g_m/g0) p_m;
+//   * Lax-Friedrichs fluxes and Euler eigenvectors (Remark 2.1).
+// The types are templated so that the FP64 path and the mixed path (FP64
+// coefficients / smoothness indicators / weights, FP32 point values and
+// fluxes) share one code path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hwenou {
+
+enum : int { EQ_ADVECTION = 0, EQ_BURGERS = 1, EQ_EULER = 2 };
+enum : int { W_SCALE_INVARIANT = 0, W_ZQ = 1, W_LINEAR = 2 };
+enum : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
+
+// Gauss points on [-1/2, 1/2]: 3-point Gauss (sqrt(15)/10, weights 5/18, 4/9)
+// and 4-point Gauss-Lobatto (1/2, sqrt(5)/10, weights 1/12, 5/12).
+constexpr double G3S = 0.38729833462074168852;
+constexpr double G3W0 = 5.0 / 18.0;
+constexpr double G3W1 = 4.0 / 9.0;
+constexpr double GL4S = 0.22360679774997896964;
+constexpr double GL4W0 = 1.0 / 12.0;
+constexpr double GL4W1 = 5.0 / 12.0;
+
+// Runtime scheme parameters shared by every kernel.
+struct SchemeParams {
+  double adv_x, adv_y;  // advection velocity
+  double gas_gamma;     // ratio of specific heats
+  double gamma_low;     // linear weight of each linear polynomial
+  double eps;           // epsilon of the nonlinear weights
+  int weights;          // W_*
+};
+
+__device__ __forceinline__ int wrap_index(int i, int n, int bc_lo, int bc_hi) {
+  if (i < 0) return bc_lo == BC_PERIODIC ? (i + n) : 0;  // |i| <= 2 <= n for periodic
+  if (i >= n) return bc_hi == BC_PERIODIC ? (i - n) : n - 1;
+  return i;
+}
+
+// ---------------------------------------------------------------------------
+// nonlinear weights (Step 3), returned as the combination factors
+//   a   = w0 / g0          (factor of p0)
+//   b_m = w_m - a g_m      (factor of p_m)
+// so that u_i = a p0 + sum_m b_m p_m.  Always evaluated in FP64.
+// ---------------------------------------------------------------------------
+template <int NM>
+__device__ __forceinline__ void combine_factors(const SchemeParams& P, const double (&beta)[NM + 1],
+                                                double u_ave, double& a, double (&b)[NM]) {
+  const double gl = P.gamma_low;
+  const double g0 = 1.0 - NM * gl;
+  if (P.weights == W_LINEAR) {
+    a = 1.0;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) b[m] = 0.0;
+    return;
+  }
+  if (P.weights == W_ZQ) u_ave = 1.0;
+  double t = 0.0;
+#pragma unroll
+  for (int m = 1; m <= NM; ++m) t += fabs(beta[0] - beta[m]);
+  t *= (1.0 / NM);
+  const double tau = t * t;
+  double wt[NM + 1];
+  wt[0] = g0 * (1.0 + tau / (beta[0] * u_ave + P.eps));
+  double sum = wt[0];
+#pragma unroll
+  for (int m = 1; m <= NM; ++m) {
+    wt[m] = gl * (1.0 + tau / (beta[m] * u_ave + P.eps));
+    sum += wt[m];
+  }
+  const double inv = 1.0 / sum;
+  const double w0 = wt[0] * inv;
+  a = w0 / g0;
+#pragma unroll
+  for (int m = 0; m < NM; ++m) b[m] = wt[m + 1] * inv - a * gl;
+}
+
+// ---------------------------------------------------------------------------
+// 1D: one scalar reconstruction
+// ---------------------------------------------------------------------------
+// Input: u_{i-1}, u_i, u_{i+1}, v_{i-1}, v_{i+1} (FP64).  Output: combined
+// polynomial coefficients C0..C4 in xi (in TR) and the modified moment.
+template <class TR>
+struct Poly1 {
+  TR c[5];
+};
+
+__device__ __forceinline__ void p0_coeffs_1d(double um, double u0, double up, double vm, double vp,
+                                             double (&c)[5]) {
+  const double su = um + up, du = up - um, sv = vm + vp, dv = vp - vm;
+  c[0] = (-43.0 / 384.0) * su + (235.0 / 192.0) * u0 + (27.0 / 64.0) * dv;
+  c[1] = (63.0 / 76.0) * du - (75.0 / 19.0) * sv;
+  c[2] = (23.0 / 16.0) * su - (23.0 / 8.0) * u0 - (45.0 / 8.0) * dv;
+  c[3] = (-5.0 / 19.0) * du + (60.0 / 19.0) * sv;
+  c[4] = (-5.0 / 8.0) * su + (5.0 / 4.0) * u0 + (15.0 / 4.0) * dv;
+}
+
+__device__ __forceinline__ double beta0_1d(const double (&c)[5]) {
+  const double t1 = c[1] + 0.25 * c[3];
+  const double t2 = c[2] + (63.0 / 130.0) * c[4];
+  return t1 * t1 + (13.0 / 3.0) * t2 * t2 + (781.0 / 20.0) * c[3] * c[3] +
+         (1421461.0 / 2275.0) * c[4] * c[4];
+}
+
+// c: p0 coefficients; slopes s1 = u_i - u_{i-1}, s2 = u_{i+1} - u_i; u0 = u_i.
+// |u| values for u_ave are passed separately (characteristic or scalar).
+template <class TR>
+__device__ __forceinline__ void hweno_1d(const SchemeParams& P, const double (&c)[5], double u0,
+                                         double s1, double s2, double aum, double au0, double aup,
+                                         TR (&C)[5]) {
+  double beta[3] = {beta0_1d(c), s1 * s1, s2 * s2};
+  const double ua = (aum + au0 + aup) * (1.0 / 3.0);
+  double a, b[2];
+  combine_factors<2>(P, beta, ua * ua, a, b);
+  C[0] = (TR)(a * c[0] + (b[0] + b[1]) * u0);
+  C[1] = (TR)(a * c[1] + b[0] * s1 + b[1] * s2);
+  C[2] = (TR)(a * c[2]);
+  C[3] = (TR)(a * c[3]);
+  C[4] = (TR)(a * c[4]);
+}
+
+// values at xi = -1/2, -sqrt5/10, +sqrt5/10, +1/2 and the x-moment
+template <class TR>
+__device__ __forceinline__ void eval_1d(const TR (&C)[5], TR (&pt)[4], TR& mom) {
+  const TR h = (TR)0.5, s = (TR)GL4S;
+  const TR Eh = C[0] + h * h * (C[2] + h * h * C[4]);
+  const TR Oh = h * (C[1] + h * h * C[3]);
+  const TR Es = C[0] + s * s * (C[2] + s * s * C[4]);
+  const TR Os = s * (C[1] + s * s * C[3]);
+  pt[0] = Eh - Oh;
+  pt[1] = Es - Os;
+  pt[2] = Es + Os;
+  pt[3] = Eh + Oh;
+  mom = C[1] * (TR)(1.0 / 12.0) + C[3] * (TR)(1.0 / 80.0);
+}
+
+// ---------------------------------------------------------------------------
+// 2D: stencil data and one scalar reconstruction
+// ---------------------------------------------------------------------------
+// Stencil layout: u[0..8] = cells 1..9 (label = 5 + a + 3b for offset (a, b)),
+// v[0..3] = v at cells 2, 4, 6, 8, w[0..3] = w at cells 2, 4, 6, 8.
+struct Sten2 {
+  double u[9];
+  double v[4];
+  double w[4];
+};
+
+__device__ __forceinline__ void p0_coeffs_2d(const Sten2& s, double (&c)[15]) {
+  const double u1 = s.u[0], u2 = s.u[1], u3 = s.u[2], u4 = s.u[3], u5 = s.u[4], u6 = s.u[5],
+               u7 = s.u[6], u8 = s.u[7], u9 = s.u[8];
+  const double v2 = s.v[0], v4 = s.v[1], v6 = s.v[2], v8 = s.v[3];
+  const double w2 = s.w[0], w4 = s.w[1], w6 = s.w[2], w8 = s.w[3];
+  const double corner = u1 + u3 + u7 + u9;
+  const double ux = -u1 + u3 - u7 + u9;  // x-odd corner combination
+  const double uy = -u1 - u3 + u7 + u9;  // y-odd corner combination
+  const double uxy = u1 - u3 - u7 + u9;  // xy-odd corner combination
+  c[0] = (1.0 / 576.0) * corner - (133.0 / 1152.0) * (u2 + u4 + u6 + u8) + (419.0 / 288.0) * u5 +
+         (27.0 / 64.0) * (v6 - v4) + (27.0 / 64.0) * (w8 - w2);
+  c[1] = (-1.0 / 48.0) * ux + (397.0 / 456.0) * (u6 - u4) - (75.0 / 19.0) * (v4 + v6);
+  c[2] = (-1.0 / 48.0) * uy + (397.0 / 456.0) * (u8 - u2) - (75.0 / 19.0) * (w2 + w8);
+  c[3] = (-1.0 / 48.0) * corner + (1.0 / 24.0) * (u2 + u8) + (71.0 / 48.0) * (u4 + u6) -
+         (71.0 / 24.0) * u5 + (45.0 / 8.0) * (v4 - v6);
+  c[4] = (-7.0 / 22.0) * uxy + (75.0 / 11.0) * (v8 - v2) + (75.0 / 11.0) * (w6 - w4);
+  c[5] = (-1.0 / 48.0) * corner + (71.0 / 48.0) * (u2 + u8) + (1.0 / 24.0) * (u4 + u6) -
+         (71.0 / 24.0) * u5 + (45.0 / 8.0) * (w2 - w8);
+  c[6] = (5.0 / 19.0) * (u4 - u6) + (60.0 / 19.0) * (v4 + v6);
+  c[7] = 0.25 * uy + 0.5 * (u2 - u8);
+  c[8] = 0.25 * ux + 0.5 * (u4 - u6);
+  c[9] = (5.0 / 19.0) * (u2 - u8) + (60.0 / 19.0) * (w2 + w8);
+  c[10] = (-5.0 / 8.0) * (u4 + u6) + 1.25 * u5 + (15.0 / 4.0) * (v6 - v4);
+  c[11] = (5.0 / 22.0) * uxy + (60.0 / 11.0) * (v2 - v8);
+  c[12] = 0.25 * corner - 0.5 * (u2 + u4 + u6 + u8) + u5;
+  c[13] = (5.0 / 22.0) * uxy + (60.0 / 11.0) * (w4 - w6);
+  c[14] = (-5.0 / 8.0) * (u2 + u8) + 1.25 * u5 + (15.0 / 4.0) * (w8 - w2);
+}
+
+__device__ __forceinline__ double sq(double x) { return x * x; }
+
+// printed sum-of-squares form of the smoothness indicator of p0 in 2D
+__device__ __forceinline__ double beta0_2d(const double (&c)[15]) {
+  double b = 0.5 * (sq(c[1] + 0.5 * c[6]) + sq(c[1] + (1.0 / 6.0) * c[8]) +
+                    sq(c[2] + (1.0 / 6.0) * c[7]) + sq(c[2] + 0.5 * c[9]));
+  b += (13.0 / 6.0) * (sq(c[3] + (63.0 / 65.0) * c[10]) + sq(c[3] + (1.0 / 6.0) * c[12]) +
+                       sq(c[5] + (1.0 / 6.0) * c[12]) + sq(c[5] + (63.0 / 65.0) * c[14]));
+  b += (7.0 / 12.0) * (sq(c[4] + (17.0 / 35.0) * c[11]) + sq(c[4] + (17.0 / 35.0) * c[13]));
+  b += (3119.0 / 80.0) * sq(c[6] + (5.0 / 9357.0) * c[8]);
+  b += (3379.0 / 720.0) * sq(c[7] + (15.0 / 3379.0) * c[9]);
+  b += (2634769.0 / 561420.0) * sq(c[8]) + (2634769.0 / 67580.0) * sq(c[9]);
+  b += (5676583.0 / 9100.0) * sq(c[10] + (3185.0 / 11353166.0) * c[12]);
+  b += (709573.0 / 16800.0) * sq(c[11] + (1155.0 / 709573.0) * c[13]);
+  b += (230094013357.0 / 12261419280.0) * sq(c[12] + (2145748374.0 / 230094013357.0) * c[14]);
+  b += (31468281769.0 / 745051650.0) * sq(c[13]);
+  b += (25118160529227568.0 / 40266452337475.0) * sq(c[14]);
+  return b;
+}
+
+// Linear polynomials p1..p4 share four one-sided differences:
+//   dL = u5 - u4, dR = u6 - u5, dB = u5 - u2, dT = u8 - u5
+// p1 = u5 + dL xi + dB eta, p2 = u5 + dR xi + dB eta,
+// p3 = u5 + dL xi + dT eta, p4 = u5 + dR xi + dT eta.
+// Combined coefficients C from p0 coefficients c, the centre value u5 and
+// the differences; |u| of cells 2, 4, 5, 6, 8 for u_ave.
+template <class TR>
+__device__ __forceinline__ void hweno_2d(const SchemeParams& P, const double (&c)[15], double u5,
+                                         double dL, double dR, double dB, double dT,
+                                         double abs_sum5, TR (&C)[15]) {
+  const double lL = dL * dL, lR = dR * dR, lB = dB * dB, lT = dT * dT;
+  double beta[5] = {beta0_2d(c), lL + lB, lR + lB, lL + lT, lR + lT};
+  const double ua = abs_sum5 * 0.2;
+  double a, b[4];
+  combine_factors<4>(P, beta, ua * ua, a, b);
+  C[0] = (TR)(a * c[0] + ((b[0] + b[1]) + (b[2] + b[3])) * u5);
+  C[1] = (TR)(a * c[1] + (b[0] + b[2]) * dL + (b[1] + b[3]) * dR);
+  C[2] = (TR)(a * c[2] + (b[0] + b[1]) * dB + (b[2] + b[3]) * dT);
+#pragma unroll
+  for (int n = 3; n < 15; ++n) C[n] = (TR)(a * c[n]);
+}
+
+// moments of the combined polynomial: int C xi, int C eta over the cell
+template <class TR>
+__device__ __forceinline__ TR qv_2d(const TR (&C)[15]) {
+  return C[1] * (TR)(1.0 / 12.0) + C[6] * (TR)(1.0 / 80.0) + C[8] * (TR)(1.0 / 144.0);
+}
+template <class TR>
+__device__ __forceinline__ TR qw_2d(const TR (&C)[15]) {
+  return C[2] * (TR)(1.0 / 12.0) + C[9] * (TR)(1.0 / 80.0) + C[7] * (TR)(1.0 / 144.0);
+}
+
+// Restriction of the quartic C(xi, eta) to eta = e as a polynomial in xi
+// (d0..d4), and to xi = e as a polynomial in eta (dual).
+template <class TR>
+__device__ __forceinline__ void restrict_eta(const TR (&C)[15], TR e, TR (&d)[5]) {
+  d[0] = C[0] + e * (C[2] + e * (C[5] + e * (C[9] + e * C[14])));
+  d[1] = C[1] + e * (C[4] + e * (C[8] + e * C[13]));
+  d[2] = C[3] + e * (C[7] + e * C[12]);
+  d[3] = C[6] + e * C[11];
+  d[4] = C[10];
+}
+template <class TR>
+__device__ __forceinline__ void restrict_xi(const TR (&C)[15], TR e, TR (&d)[5]) {
+  d[0] = C[0] + e * (C[1] + e * (C[3] + e * (C[6] + e * C[10])));
+  d[1] = C[2] + e * (C[4] + e * (C[7] + e * C[11]));
+  d[2] = C[5] + e * (C[8] + e * C[12]);
+  d[3] = C[9] + e * C[13];
+  d[4] = C[14];
+}
+// 1D quartic d at +-1/2 (edges) and +-sqrt15/10, 0 (Gauss points)
+template <class TR>
+__device__ __forceinline__ void eval5(const TR (&d)[5], TR& em, TR& ep, TR& gm, TR& g0, TR& gp) {
+  const TR h2 = (TR)0.25, s = (TR)G3S, s2 = (TR)(G3S * G3S);
+  const TR Eh = d[0] + h2 * (d[2] + h2 * d[4]);
+  const TR Oh = (TR)0.5 * (d[1] + h2 * d[3]);
+  const TR Es = d[0] + s2 * (d[2] + s2 * d[4]);
+  const TR Os = s * (d[1] + s2 * d[3]);
+  em = Eh - Oh;
+  ep = Eh + Oh;
+  gm = Es - Os;
+  g0 = d[0];
+  gp = Es + Os;
+}
+
+// ---------------------------------------------------------------------------
+// Euler: primitive quantities and eigenvectors (ideal gas)
+// ---------------------------------------------------------------------------
+// Left eigenvectors L (rows) and right eigenvectors R (columns) of the flux
+// Jacobian in direction DIR at the conserved state U.  NC = 3 (1D) or 4 (2D).
+// 1D right eigenvectors: (1, u-c, H-uc), (1, u, u^2/2), (1, u+c, H+uc).
+// 2D, x: (1, u-c, v, H-uc), (1, u, v, q^2/2), (0, 0, 1, v), (1, u+c, v, H+uc);
+// 2D, y: (1, u, v-c, H-vc), (1, u, v, q^2/2), (0, 1, 0, u), (1, u, v+c, H+vc).
+template <int NC, int DIR>
+__device__ __forceinline__ void euler_eig(double gm1, const double (&U)[NC], double (&L)[NC][NC],
+                                          double (&R)[NC][NC]) {
+  const double rinv = 1.0 / U[0];
+  const double u = U[1] * rinv;
+  const double v = NC == 4 ? U[2] * rinv : 0.0;
+  const double q2 = u * u + v * v;
+  const double p = gm1 * (U[NC - 1] - 0.5 * U[0] * q2);
+  const double c2 = (gm1 + 1.0) * p * rinv;
+  const double c = sqrt(c2);
+  const double ci = 1.0 / c;
+  const double H = (U[NC - 1] + p) * rinv;
+  const double b1 = gm1 / c2;
+  const double b2 = 0.5 * b1 * q2;
+  if constexpr (NC == 3) {
+    L[0][0] = 0.5 * (b2 + u * ci); L[0][1] = -0.5 * (b1 * u + ci); L[0][2] = 0.5 * b1;
+    L[1][0] = 1.0 - b2;            L[1][1] = b1 * u;               L[1][2] = -b1;
+    L[2][0] = 0.5 * (b2 - u * ci); L[2][1] = -0.5 * (b1 * u - ci); L[2][2] = 0.5 * b1;
+    R[0][0] = 1.0;        R[0][1] = 1.0;          R[0][2] = 1.0;
+    R[1][0] = u - c;      R[1][1] = u;            R[1][2] = u + c;
+    R[2][0] = H - u * c;  R[2][1] = 0.5 * u * u;  R[2][2] = H + u * c;
+  } else if constexpr (DIR == 0) {
+    L[0][0] = 0.5 * (b2 + u * ci); L[0][1] = -0.5 * (b1 * u + ci); L[0][2] = -0.5 * b1 * v; L[0][3] = 0.5 * b1;
+    L[1][0] = 1.0 - b2;            L[1][1] = b1 * u;               L[1][2] = b1 * v;        L[1][3] = -b1;
+    L[2][0] = -v;                  L[2][1] = 0.0;                  L[2][2] = 1.0;           L[2][3] = 0.0;
+    L[3][0] = 0.5 * (b2 - u * ci); L[3][1] = -0.5 * (b1 * u - ci); L[3][2] = -0.5 * b1 * v; L[3][3] = 0.5 * b1;
+    R[0][0] = 1.0;       R[0][1] = 1.0;      R[0][2] = 0.0; R[0][3] = 1.0;
+    R[1][0] = u - c;     R[1][1] = u;        R[1][2] = 0.0; R[1][3] = u + c;
+    R[2][0] = v;         R[2][1] = v;        R[2][2] = 1.0; R[2][3] = v;
+    R[3][0] = H - u * c; R[3][1] = 0.5 * q2; R[3][2] = v;   R[3][3] = H + u * c;
+  } else {
+    L[0][0] = 0.5 * (b2 + v * ci); L[0][1] = -0.5 * b1 * u; L[0][2] = -0.5 * (b1 * v + ci); L[0][3] = 0.5 * b1;
+    L[1][0] = 1.0 - b2;            L[1][1] = b1 * u;        L[1][2] = b1 * v;               L[1][3] = -b1;
+    L[2][0] = -u;                  L[2][1] = 1.0;           L[2][2] = 0.0;                  L[2][3] = 0.0;
+    L[3][0] = 0.5 * (b2 - v * ci); L[3][1] = -0.5 * b1 * u; L[3][2] = -0.5 * (b1 * v - ci); L[3][3] = 0.5 * b1;
+    R[0][0] = 1.0;       R[0][1] = 1.0;      R[0][2] = 0.0; R[0][3] = 1.0;
+    R[1][0] = u;         R[1][1] = u;        R[1][2] = 1.0; R[1][3] = u;
+    R[2][0] = v - c;     R[2][1] = v;        R[2][2] = 0.0; R[2][3] = v + c;
+    R[3][0] = H - v * c; R[3][1] = 0.5 * q2; R[3][2] = u;   R[3][3] = H + v * c;
+  }
+}
+
+// physical flux in direction DIR (0 = f, 1 = g) of the conserved state U
+template <int EQ, int NC, int DIR, class T>
+__device__ __forceinline__ void phys_flux(const SchemeParams& P, const T (&U)[NC], T (&F)[NC]) {
+  if constexpr (EQ == EQ_ADVECTION) {
+    F[0] = (T)(DIR == 0 ? P.adv_x : P.adv_y) * U[0];
+  } else if constexpr (EQ == EQ_BURGERS) {
+    F[0] = (T)0.5 * U[0] * U[0];
+  } else if constexpr (NC == 3) {
+    const T gm1 = (T)(P.gas_gamma - 1.0);
+    const T u = U[1] / U[0];
+    const T p = gm1 * (U[2] - (T)0.5 * U[1] * u);
+    F[0] = U[1];
+    F[1] = U[1] * u + p;
+    F[2] = u * (U[2] + p);
+  } else {
+    const T gm1 = (T)(P.gas_gamma - 1.0);
+    const T rinv = (T)1 / U[0];
+    const T u = U[1] * rinv, v = U[2] * rinv;
+    const T p = gm1 * (U[3] - (T)0.5 * (U[1] * u + U[2] * v));
+    if constexpr (DIR == 0) {
+      F[0] = U[1];
+      F[1] = U[1] * u + p;
+      F[2] = U[2] * u;
+      F[3] = u * (U[3] + p);
+    } else {
+      F[0] = U[2];
+      F[1] = U[1] * v;
+      F[2] = U[2] * v + p;
+      F[3] = v * (U[3] + p);
+    }
+  }
+}
+
+// Lax-Friedrichs flux 1/2 [F(u-) + F(u+) - alpha (u+ - u-)]
+template <int EQ, int NC, int DIR, class T>
+__device__ __forceinline__ void lf_flux(const SchemeParams& P, const T (&um)[NC], const T (&up)[NC],
+                                        T alpha, T (&fh)[NC]) {
+  T fm[NC], fp[NC];
+  phys_flux<EQ, NC, DIR, T>(P, um, fm);
+  phys_flux<EQ, NC, DIR, T>(P, up, fp);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) fh[k] = (T)0.5 * (fm[k] + fp[k] - alpha * (up[k] - um[k]));
+}
+
+// wave speeds |f'(u)| (x) and |g'(u)| (y) of a cell average, and validity
+template <int EQ, int NC>
+__device__ __forceinline__ bool wave_speeds(const SchemeParams& P, const double (&U)[NC], double& sx,
+                                            double& sy) {
+  if constexpr (EQ == EQ_ADVECTION) {
+    sx = fabs(P.adv_x);
+    sy = fabs(P.adv_y);
+    return isfinite(U[0]);
+  } else if constexpr (EQ == EQ_BURGERS) {
+    sx = sy = fabs(U[0]);
+    return isfinite(U[0]);
+  } else {
+    const double rinv = 1.0 / U[0];
+    const double u = U[1] * rinv;
+    const double v = NC == 4 ? U[2] * rinv : 0.0;
+    const double p = (P.gas_gamma - 1.0) * (U[NC - 1] - 0.5 * U[0] * (u * u + v * v));
+    const double c = sqrt(P.gas_gamma * p * rinv);
+    sx = fabs(u) + c;
+    sy = fabs(v) + c;
+    bool ok = U[0] > 0.0 && p > 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) ok = ok && isfinite(U[k]);
+    return ok;
+  }
+}
+
+// wave-wide max of a non-negative double (64 lanes)
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+// atomic max for non-negative doubles through their IEEE bit patterns
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(addr),
+            static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+}  // namespace hwenou

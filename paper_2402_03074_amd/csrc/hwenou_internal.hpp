@@ -1,0 +1,80 @@
+// Internal interface between the host library (hwenou_api.cpp) and the
+// kernel translation units.  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hwenou_device.hpp"
+
+namespace hwenou {
+
+// One problem instance as the kernels see it.
+struct InstDev {
+  int nx, ny;        // cells (ny = 1 in 1D)
+  int bc[4];         // x-lo, x-hi, y-lo, y-hi (BC_*)
+  double dx, dy;     // mesh sizes
+  long long offset;  // first cell of the instance in each component plane
+};
+
+// One work item.  1D: (inst, first cell of a 62-cell tile).  2D: (inst,
+// strip, first row, end row) -- a strip is 62 output columns marched upward.
+struct WorkItem {
+  int inst, a, b, c;
+};
+
+// Lanes of a wave that produce output; lane 0 and lane 63 only reconstruct
+// the neighbouring cells whose interface values the strip needs.
+constexpr int kStripWidth = 62;
+
+template <class TM>
+struct StageArgs {
+  SchemeParams P;
+  const InstDev* inst;
+  const double* dt;     // [n_inst]
+  const double* alpha;  // [n_inst][2]
+  const int* done;      // [n_inst] or nullptr
+  const double* u_in;   // [nc][plane]
+  const TM* m_in;       // [dim][nc][plane]
+  const double* u_base; // u^n for stages 1, 2
+  TM* m_base;           // v^_n (and w^_n): written by stage 0, read by stages 1, 2
+  double* u_out;
+  TM* m_out;
+  double* alpha_next;   // [n_inst][2] or nullptr: max wave speed of the output
+  int* status;          // set to 1 on a non-physical or non-finite output
+  long long plane;      // cells per component plane
+  const WorkItem* work;
+  const int* work_ptr;  // wave w handles work[work_ptr[w] .. work_ptr[w+1])
+  int n_waves;
+  int stage;            // 0, 1, 2
+};
+
+// kernel launchers (one per translation unit); return hipSuccess or the launch error
+hipError_t launch_stage_1d(int eq, bool char_decomp, bool mixed, const void* args, int blocks,
+                           int threads, hipStream_t s);
+hipError_t launch_stage_2d(int eq, bool char_decomp, bool mixed, const void* args, int blocks,
+                           int threads, hipStream_t s);
+
+// auxiliary kernels
+struct AuxArgs {
+  SchemeParams P;
+  int eq, dim, n_inst;
+  const InstDev* inst;
+  long long plane;
+  const double* u;       // [nc][plane]
+  double* alpha;         // [n_inst][2]
+  double* dt;            // [n_inst]
+  double* t;             // [n_inst]
+  int* steps;            // [n_inst]
+  int* done;             // [n_inst]
+  int* status;
+  double* alpha_next;    // [n_inst][2]
+  double cfl, t_final;
+  int max_steps;
+  int* all_done;         // 1 when every instance is done
+};
+hipError_t launch_max_wavespeed(const AuxArgs& a, hipStream_t s);
+hipError_t launch_dt(const AuxArgs& a, hipStream_t s);
+hipError_t launch_finish(const AuxArgs& a, hipStream_t s);
+
+}  // namespace hwenou

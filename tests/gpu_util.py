@@ -1,0 +1,93 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C-ABI and the
+oracle on the same seeded inputs."""
+import numpy as np
+
+import paper_2402_03074_amd as H
+
+
+def rel_linf(a, b):
+    """max |a - b| / max |b| over one array."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rel_err(a, b, lead):
+    """max over the leading `lead` indices (components, moment direction) of
+    rel_linf of the remaining cell array."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return max(rel_linf(a[idx], b[idx]) for idx in np.ndindex(*a.shape[:lead]))
+
+
+def state_err(P, got, ref):
+    """(error of the averages, error of the moments), per-array relative L-inf."""
+    return rel_err(got[0], ref[0], 1), rel_err(got[1], ref[1], 2)
+
+
+def to_gpu(x, dtype=None):
+    import torch
+    t = torch.tensor(np.ascontiguousarray(x), device="cuda")
+    return t if dtype is None else t.to(dtype)
+
+
+def solver_for(P, precision="fp64", **kw):
+    """Single-instance GPU solver mirroring an oracle Problem."""
+    bc = [{0: "periodic", 1: "transmissive"}[b] for b in P.bc]
+    if P.dim == 1:
+        inst = H.make_inst(P.nx, 1, P.domain[:2], bc)
+    else:
+        inst = H.make_inst(P.nx, P.ny, P.domain, bc)
+    p = P.params
+    weights = {0: "scale_invariant", 1: "zq", 2: "linear"}[p.weights]
+    return H.Solver(P.dim, P.eq, [inst], precision=precision, weights=weights,
+                    char_decomp=bool(p.char_decomp), adv=(p.adv_x, p.adv_y),
+                    gas_gamma=p.gas_gamma, gamma_low=p.gamma_low, eps=p.eps, **kw)
+
+
+def flat(P, u, m):
+    """Oracle layout -> C-ABI layout (cells flattened, x fastest)."""
+    return u.reshape(P.ncomp, -1), m.reshape(P.dim, P.ncomp, -1)
+
+
+def unflat(P, u, m):
+    return u.reshape(P.shape), m.reshape((P.dim,) + P.shape)
+
+
+def gpu_three_stages(S, P, u0, m0, dt, alpha, inputs=None):
+    """Run stages 0, 1, 2 on the GPU.  inputs: optional list of the stage
+    inputs (u, m) for stages 1 and 2 (taken from the oracle); otherwise the
+    GPU's own outputs are chained.  Returns the three stage outputs (numpy,
+    oracle layout)."""
+    import torch
+    mdt = S.mom_dtype
+    uf, mf = flat(P, u0, m0)
+    ug, mg = to_gpu(uf), to_gpu(mf, mdt)
+    al = to_gpu(np.array([[alpha[0], alpha[1] if len(alpha) > 1 else 0.0]]))
+    dtg = to_gpu(np.array([dt]))
+    outs = []
+    cur = (ug, mg)
+    for s in range(3):
+        if s > 0 and inputs is not None:
+            ui, mi = flat(P, *inputs[s - 1])
+            cur = (to_gpu(ui), to_gpu(mi, mdt))
+        uo, mo = S.empty_state()
+        S.stage(s, dtg, al, cur[0], cur[1], uo, mo)
+        torch.cuda.synchronize()
+        outs.append(unflat(P, uo.cpu().numpy(), mo.double().cpu().numpy()))
+        if s == 0:
+            keep0 = (ug, mg)  # the base must stay alive until stage 2
+        cur = (uo, mo)
+    del keep0
+    return outs
+
+
+def oracle_three_stages(P, u0, m0, dt, alpha):
+    outs = []
+    u, m, base = P.stage(0, dt, alpha, u0, m0)
+    outs.append((u, m))
+    u, m, _ = P.stage(1, dt, alpha, u, m, base)
+    outs.append((u, m))
+    u, m, _ = P.stage(2, dt, alpha, u, m, base)
+    outs.append((u, m))
+    return outs

@@ -1,0 +1,75 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and rejects invalid descriptions before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2402_03074_amd as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hwenou.h")).read()
+    return sorted(set(re.findall(r"\b(hwenou_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    assert set(_declared()) == set(H.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(H.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_strerror_codes():
+    for code in range(6):
+        assert isinstance(H.strerror(code), str) and H.strerror(code)
+    assert "non-physical" in H.strerror(H.HWENOU_ENONPHYSICAL)
+
+
+def _create(desc, insts):
+    arr = (H.Inst * len(insts))(*insts)
+    h = C.c_void_p()
+    rc = H.lib().hwenou_create(C.byref(desc), len(insts), arr, None, C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("field,value", [("dim", 3), ("eq", 7), ("precision", 2),
+                                         ("weights", 5), ("gamma_low", 0.5),
+                                         ("gas_gamma", 1.0), ("eps", -1.0)])
+def test_create_rejects_bad_description(field, value):
+    d = H.make_desc(1, "euler")
+    setattr(d, field, value)
+    rc, h = _create(d, [H.make_inst(10)])
+    assert rc == H.HWENOU_EINVAL and not h.value
+
+
+def test_create_rejects_bad_instances():
+    d = H.make_desc(2, "euler")
+    assert _create(d, [H.make_inst(2, 10, (0, 1, 0, 1))])[0] == H.HWENOU_EINVAL
+    assert _create(d, [H.make_inst(10, 2, (0, 1, 0, 1))])[0] == H.HWENOU_EINVAL
+    # overlapping instances
+    a = H.make_inst(10, 10, (0, 1, 0, 1), offset=0)
+    b = H.make_inst(10, 10, (0, 1, 0, 1), offset=50)
+    assert _create(d, [a, b])[0] == H.HWENOU_EINVAL
+    # empty domain
+    assert _create(d, [H.make_inst(10, 10, (1, 1, 0, 1))])[0] == H.HWENOU_EINVAL
+    # bad boundary condition
+    c = H.make_inst(10, 10, (0, 1, 0, 1))
+    c.bc[2] = 9
+    assert _create(d, [c])[0] == H.HWENOU_EINVAL
+    assert H.lib().hwenou_create(C.byref(d), 0, None, None, C.byref(C.c_void_p())) == \
+        H.HWENOU_EINVAL
+
+
+def test_calls_reject_null_handle():
+    L = H.lib()
+    assert L.hwenou_destroy(None) == H.HWENOU_EINVAL
+    assert L.hwenou_stage(None, 0, None, None, None, None, None, None) == H.HWENOU_EINVAL
+    assert L.hwenou_advance(None, None, None, 0.5, 1.0, 1, None, None) == H.HWENOU_EINVAL
+    assert L.hwenou_set_launch(None, 1, 0) == H.HWENOU_EINVAL
