@@ -1,0 +1,201 @@
+"""Benchmark of the HWENO-U hot path on one MI355X.
+
+Workload: 2D Euler (gamma = 1.4) on a 2048 x 2048 periodic grid of [0, 10]^2,
+seeded four-quadrant Riemann data (rho in [0.1, 1.5], p in [0.03, 1.5],
+u, v in [-0.5, 0.5]) times an isentropic vortex of strength 5, CFL 0.6,
+modified SSP-RK3.  One benchmark step = one full Runge-Kutta step: the max
+wave speed / dt, and three fused stages (reconstruction, weights, moment
+modification, fluxes, update), replayed from a captured HIP graph.
+
+Reported: cell-stage updates per second of the mixed form (`value`) and of the
+plain FP64 form, the mixed-vs-FP64 L1 difference after the timed run, the
+stage kernel's roofline position, and the CPU oracle on a bounded sample.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "2D Euler cell-stage updates/s, mixed vs FP64 at fixed L1 error; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = 78.6  # FP64 vector (= non-packed FP32 vector) on MI355X
+
+# algorithmic HBM bytes per cell and stage (state read, base read, write;
+# stage 0 also writes the modified moments); 2D Euler: 4 components
+def stage_bytes(precision, stage):
+    mb = 8 if precision == "fp64" else 4
+    state = 4 * 8 + 2 * 4 * mb  # averages FP64 + two moment directions
+    moments = 2 * 4 * mb
+    if stage == 0:
+        return state + state + moments
+    return state + (4 * 8 + moments) + state
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--size", type=int, default=2048)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--precisions", default="mixed,fp64")
+    return p.parse_args()
+
+
+def run_precision(H, torch, u0, m0, n, precision, steps, warmup):
+    inst = H.make_inst(n, n, (0.0, 10.0, 0.0, 10.0), "periodic")
+    S = H.Solver(2, "euler", [inst], precision=precision)
+    ug = torch.tensor(u0.reshape(4, -1), device="cuda")
+    mg = torch.tensor(m0.reshape(2, 4, -1), device="cuda").to(S.mom_dtype)
+    # warm-up steps (untimed), then exactly `steps` timed steps
+    if warmup > 0:
+        S.advance(ug, mg, 0.6, 1e30, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    tg, sg = S.advance(ug, mg, 0.6, 1e30, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    assert sg == [steps], sg
+
+    # stage kernels timed one by one on the stream they run on (the handle's
+    # stream is torch's current stream for hwenou_stage)
+    alpha = S.max_wavespeed(ug)
+    a = alpha.cpu().numpy()[0]
+    dx = 10.0 / n
+    dt = torch.tensor([0.6 / (a[0] / dx + a[1] / dx)], dtype=torch.float64, device="cuda")
+    u1, m1 = S.empty_state()
+    u2, m2 = S.empty_state()
+    u3, m3 = S.empty_state()
+    reps = 5
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+    for r in range(reps):
+        ev = evs[r]
+        ev[0].record()
+        S.stage(0, dt, alpha, ug, mg, u1, m1)
+        ev[1].record()
+        S.stage(1, dt, alpha, u1, m1, u2, m2)
+        ev[2].record()
+        S.stage(2, dt, alpha, u2, m2, u3, m3)
+        ev[3].record()
+    torch.cuda.synchronize()
+    stage_ms = [sum(evs[r][s].elapsed_time(evs[r][s + 1]) for r in range(reps)) / reps
+                for s in range(3)]
+    status = H.hwenou_status(S.h)
+    out = ug.cpu().numpy(), mg.double().cpu().numpy()
+    S.close()
+    del ug, mg, u1, m1, u2, m2, u3, m3
+    torch.cuda.empty_cache()
+    return {"wall_s": wall, "event_ms": ev_ms, "stage_ms": stage_ms, "state": out,
+            "t": tg[0], "status": status}
+
+
+def cpu_baseline(u0, m0, n):
+    """The oracle (plain C, FP64, OpenMP) on a bounded sample of the same
+    workload: one Runge-Kutta step (three stages) over the full grid."""
+    from oracle.driver import Problem, num_threads
+    P = Problem(2, "euler", (n, n), (0.0, 10.0, 0.0, 10.0))
+    alpha = P.max_wavespeed(u0)
+    dt = P.dt_from(alpha, 0.6)
+    t0 = time.perf_counter()
+    P.step(u0, m0, dt, alpha)
+    el = time.perf_counter() - t0
+    cs = 3 * n * n
+    return {"value": cs / el, "unit": "cell-stage/s", "cores": num_threads(),
+            "kind": "oracle",
+            "sample": f"one Runge-Kutta step (3 stages) of the same {n}x{n} 2D Euler data, "
+                      f"{cs} cell-stages in {el:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(the multi-GPU decomposition is designed, not built)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2402_03074_amd as H
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = args.size
+    print(f"[bench] generating {n}x{n} vortex + quadrant data", file=sys.stderr, flush=True)
+    u0, m0 = W.euler_2d_vortex_quadrant(n, seed=3000, q=3)
+    cells = n * n
+    results = {}
+    for prec in args.precisions.split(","):
+        print(f"[bench] {prec}: {args.warmup} warm-up + {args.steps} timed steps",
+              file=sys.stderr, flush=True)
+        results[prec] = run_precision(H, torch, u0, m0, n, prec, args.steps, args.warmup)
+        r = results[prec]
+        print(f"[bench] {prec}: {r['event_ms'] / args.steps:.3f} ms/step, stages "
+              f"{[round(x, 3) for x in r['stage_ms']]} ms", file=sys.stderr, flush=True)
+
+    def summary(prec):
+        r = results[prec]
+        ms_step = r["event_ms"] / args.steps
+        rate = cells * 3 * args.steps / (r["event_ms"] * 1e-3)
+        byts = [stage_bytes(prec, s) * cells for s in range(3)]
+        kms = sum(r["stage_ms"])
+        achieved = sum(byts) / (kms * 1e-3) / 1e9
+        return ms_step, rate, achieved, kms / 3
+
+    head = "mixed" if "mixed" in results else list(results)[0]
+    ms_step, rate, achieved, kavg = summary(head)
+    line = {
+        "metric": METRIC,
+        "value": rate,
+        "unit": "cell-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D Euler {n}x{n} periodic on [0,10]^2, seeded four-quadrant "
+                               "Riemann data x isentropic vortex (strength 5), CFL 0.6, "
+                               "modified SSP-RK3, characteristic-wise HWENO-U",
+                   "precision": head, "cells": cells, "seed": 3000},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage2d_kernel", "avg_launch_ms": kavg},
+    }
+    for prec in results:
+        if prec == head:
+            continue
+        ms2, rate2, ach2, kavg2 = summary(prec)
+        line[prec] = {"value": rate2, "ms_per_step": ms2, "hbm_achieved_gbs": ach2,
+                      "hbm_frac": ach2 / HBM_PEAK_GBS, "avg_stage_launch_ms": kavg2}
+        line["mixed_speedup_vs_fp64"] = rate / rate2 if head == "mixed" else None
+    if "mixed" in results and "fp64" in results:
+        a = results["mixed"]["state"][0]
+        b = results["fp64"]["state"][0]
+        line["mixed_vs_fp64"] = {
+            "l1_rho_diff": float(np.abs(a[0] - b[0]).mean()),
+            "rel_linf_rho_diff": float(np.abs(a[0] - b[0]).max() / np.abs(b[0]).max()),
+            "after_steps": args.warmup + args.steps}
+    line["status"] = {p: results[p]["status"] for p in results}
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(u0, m0, n)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
