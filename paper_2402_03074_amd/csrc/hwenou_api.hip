@@ -177,6 +177,8 @@ SchemeParams scheme_params(const hwenou_desc& d) {
   P.gas_gamma = d.gas_gamma;
   P.gamma_low = d.gamma_low;
   P.eps = d.eps;
+  P.inv_g0_1d = 1.0 / (1.0 - 2.0 * d.gamma_low);
+  P.inv_g0_2d = 1.0 / (1.0 - 4.0 * d.gamma_low);
   P.weights = d.weights;
   return P;
 }

@@ -42,6 +42,8 @@ struct SchemeParams {
   double gas_gamma;     // ratio of specific heats
   double gamma_low;     // linear weight of each linear polynomial
   double eps;           // epsilon of the nonlinear weights
+  double inv_g0_1d;     // 1 / (1 - 2 gamma_low)
+  double inv_g0_2d;     // 1 / (1 - 4 gamma_low)
   int weights;          // W_*
 };
 
@@ -49,6 +51,24 @@ __device__ __forceinline__ int wrap_index(int i, int n, int bc_lo, int bc_hi) {
   if (i < 0) return bc_lo == BC_PERIODIC ? (i + n) : 0;  // |i| <= 2 <= n for periodic
   if (i >= n) return bc_hi == BC_PERIODIC ? (i - n) : n - 1;
   return i;
+}
+
+// ---------------------------------------------------------------------------
+// reciprocals: hardware estimate refined by Newton-Raphson steps
+// r <- r + r (1 - x r); two steps in FP64, one in FP32.  Within a few ulp of
+// the correctly rounded quotient for the normal, finite arguments used here.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  const float e = fmaf(-x, r, 1.0f);
+  return fmaf(r, e, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -75,16 +95,16 @@ __device__ __forceinline__ void combine_factors(const SchemeParams& P, const dou
   t *= (1.0 / NM);
   const double tau = t * t;
   double wt[NM + 1];
-  wt[0] = g0 * (1.0 + tau / (beta[0] * u_ave + P.eps));
+  wt[0] = g0 * (1.0 + tau * rcp_nr(beta[0] * u_ave + P.eps));
   double sum = wt[0];
 #pragma unroll
   for (int m = 1; m <= NM; ++m) {
-    wt[m] = gl * (1.0 + tau / (beta[m] * u_ave + P.eps));
+    wt[m] = gl * (1.0 + tau * rcp_nr(beta[m] * u_ave + P.eps));
     sum += wt[m];
   }
-  const double inv = 1.0 / sum;
-  const double w0 = wt[0] * inv;
-  a = w0 / g0;
+  const double inv = rcp_nr(sum);
+  // a = w0 / g0 with w0 = wt0 / sum
+  a = (wt[0] * inv) * (NM == 2 ? P.inv_g0_1d : P.inv_g0_2d);
 #pragma unroll
   for (int m = 0; m < NM; ++m) b[m] = wt[m + 1] * inv - a * gl;
 }
@@ -332,14 +352,14 @@ __device__ __forceinline__ void phys_flux(const SchemeParams& P, const T (&U)[NC
     F[0] = (T)0.5 * U[0] * U[0];
   } else if constexpr (NC == 3) {
     const T gm1 = (T)(P.gas_gamma - 1.0);
-    const T u = U[1] / U[0];
+    const T u = U[1] * rcp_nr(U[0]);
     const T p = gm1 * (U[2] - (T)0.5 * U[1] * u);
     F[0] = U[1];
     F[1] = U[1] * u + p;
     F[2] = u * (U[2] + p);
   } else {
     const T gm1 = (T)(P.gas_gamma - 1.0);
-    const T rinv = (T)1 / U[0];
+    const T rinv = rcp_nr(U[0]);
     const T u = U[1] * rinv, v = U[2] * rinv;
     const T p = gm1 * (U[3] - (T)0.5 * (U[1] * u + U[2] * v));
     if constexpr (DIR == 0) {

@@ -2,250 +2,193 @@
 // quartic reconstruction on the 3x3 stencil (Step 1), smoothness indicators
 // and scale-invariant weights (Steps 2-3), the modified moments v^, w^, the
 // 21 point values, Lax-Friedrichs fluxes at the 3 Gauss points of every
-// edge, the right-hand sides F1, F2, F3 and the modified SSP-RK3 update.
+// edge, the right-hand sides F1, F2, F3 of Eq. (2.18) and the modified
+// SSP-RK3 update (Step 4).
 //
 // Euler: the reconstruction runs on local characteristic variables in two
-// direction-split sweeps.  The x-sweep projects with the eigenvectors of f'
-// at the cell average and yields the x-edge values, the interior values used
-// for f, and v^; the y-sweep does the same with g' for the y-edges, g and
-// w^.  Because the reconstruction is linear in the data, the p0 coefficients
-// are formed once per conserved component and projected per sweep.
-// Scalar laws (and component-wise Euler) use one reconstruction for both.
+// direction-split sweeps (Remark 2.1).  The y-sweep projects the stencil with
+// the eigenvectors of g' at the cell average and yields the y-edge values,
+// the interior values used for g, and w^; the x-sweep does the same with f'
+// for the x-edges, f and v^.  Each characteristic field is reconstructed
+// independently and the combined polynomials are mapped back to conserved
+// variables before they are evaluated.  Scalar laws (and component-wise
+// Euler) use one reconstruction for both directions.
 //
-// Mapping: a wave marches a strip of 62 output columns upward, one row per
-// step; lane l holds column strip*62 - 1 + l (lanes 0 and 63 supply the
-// neighbour columns' x-edge values).  x-interface values and fluxes move
-// between lanes by shuffles; the y-edge values of the previous row and the
-// partially accumulated right-hand side of that row stay in registers, so
-// each y-flux is evaluated once and each row is written once.  A row's stage
-// output is stored when the row above has supplied its upper y-flux.  Waves
-// take balanced runs of (strip, rows) from a per-wave work list, so one
-// persistent launch covers one large grid or many instances of uneven size.
+// Mapping: a wave (one 64-thread block) marches a strip of 62 output columns
+// upward, one row per step; lane l holds column strip*62 - 1 + l (lanes 0 and
+// 63 only supply the neighbour columns' x-edge values).  The three stencil
+// rows live in a ring of LDS rows shared by the wave; the row after next is
+// prefetched into registers while the current row is computed.  x-interface
+// values and fluxes move between lanes by shuffles.  The upper y-edge values
+// of the previous row and that row's partially accumulated right-hand side
+// stay in registers, so every flux is evaluated once and every row written
+// once.  Waves take balanced runs of (strip, rows) from a per-wave work list:
+// one persistent launch covers one large grid or many instances of uneven
+// size.
 #include "hwenou_internal.hpp"
 
 namespace hwenou {
 
-// load the 3x3 stencil of cell (i, j) (wrapped/clamped indices)
-template <int NC, class TM>
-__device__ __forceinline__ void load_stencil(const StageArgs<TM>& A, const InstDev& I, int i, int j,
-                                             Sten2 (&S)[NC]) {
-  const int nx = I.nx, ny = I.ny;
-  int xi[3], yj[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    xi[d] = wrap_index(i + d - 1, nx, I.bc[0], I.bc[1]);
-    yj[d] = wrap_index(j + d - 1, ny, I.bc[2], I.bc[3]);
-  }
-  const long long plane = A.plane;
-  const double* u = A.u_in + I.offset;
-  const TM* v = A.m_in + I.offset;
-  const TM* w = A.m_in + (long long)NC * plane + I.offset;
-#pragma unroll
-  for (int k = 0; k < NC; ++k) {
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) S[k].u[a + 3 * b] = u[k * plane + (long long)yj[b] * nx + xi[a]];
-    // cells 2, 4, 6, 8 = offsets (0,-1), (-1,0), (1,0), (0,1)
-    const long long c2 = (long long)yj[0] * nx + xi[1], c4 = (long long)yj[1] * nx + xi[0];
-    const long long c6 = (long long)yj[1] * nx + xi[2], c8 = (long long)yj[2] * nx + xi[1];
-    S[k].v[0] = (double)v[k * plane + c2];
-    S[k].v[1] = (double)v[k * plane + c4];
-    S[k].v[2] = (double)v[k * plane + c6];
-    S[k].v[3] = (double)v[k * plane + c8];
-    S[k].w[0] = (double)w[k * plane + c2];
-    S[k].w[1] = (double)w[k * plane + c4];
-    S[k].w[2] = (double)w[k * plane + c6];
-    S[k].w[3] = (double)w[k * plane + c8];
-  }
-}
-
-// Outputs of one cell's reconstruction used by the fluxes and the RHS.
-template <int NC, class TR>
-struct CellRecon {
-  TR xm[3][NC], xp[3][NC];  // u at (-1/2, eta_G), (+1/2, eta_G)
-  TR ym[3][NC], yp[3][NC];  // u at (xi_G, -1/2), (xi_G, +1/2)
-  TR volf[NC], volg[NC];    // sum_GH w_G w_H f / g at the interior Gauss points
-  TR vh[NC], wh[NC];        // modified moments
-  double u5[NC];            // cell average (stage input)
-};
+constexpr int kCols = 66;
+#ifndef HWENOU_2D_WAVES
+#define HWENOU_2D_WAVES 1
+#endif  // LDS columns: strip*62 - 2 .. strip*62 + 63
 
 __device__ __forceinline__ double g3w(int g) { return g == 1 ? G3W1 : G3W0; }
+__device__ __forceinline__ double g3x(int g) { return g == 0 ? -G3S : (g == 1 ? 0.0 : G3S); }
 
-// evaluate the x-sweep outputs (x-edges, interior f, v^) from conserved-space
-// combined coefficients Cc[m][15]
-template <int EQ, int NC, class TR>
-__device__ __forceinline__ void eval_x_sweep(const SchemeParams& P, const TR (&Cc)[NC][15],
-                                             CellRecon<NC, TR>& R, bool also_y) {
-#pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    R.volf[k] = (TR)0;
-    if (also_y) R.volg[k] = (TR)0;
-  }
-#pragma unroll
-  for (int H = 0; H < 3; ++H) {
-    const TR e = (TR)(H == 0 ? -G3S : (H == 1 ? 0.0 : G3S));
-    TR in[3][NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      TR d[5];
-      restrict_eta<TR>(Cc[k], e, d);
-      TR em, ep, gm, g0, gp;
-      eval5<TR>(d, em, ep, gm, g0, gp);
-      R.xm[H][k] = em;
-      R.xp[H][k] = ep;
-      in[0][k] = gm;
-      in[1][k] = g0;
-      in[2][k] = gp;
-    }
-#pragma unroll
-    for (int G = 0; G < 3; ++G) {
-      TR f[NC];
-      phys_flux<EQ, NC, 0, TR>(P, in[G], f);
-      const TR wgt = (TR)(g3w(G) * g3w(H));
-#pragma unroll
-      for (int k = 0; k < NC; ++k) R.volf[k] += wgt * f[k];
-      if (also_y) {
-        TR g[NC];
-        phys_flux<EQ, NC, 1, TR>(P, in[G], g);
-#pragma unroll
-        for (int k = 0; k < NC; ++k) R.volg[k] += wgt * g[k];
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NC; ++k) R.vh[k] = qv_2d<TR>(Cc[k]);
+// Primitive quantities at the cell average shared by both sweeps.
+struct Prim {
+  double u, v, c, ci, H, b1, b2, q2;
+};
+
+__device__ __forceinline__ Prim make_prim(double gm1, const double (&U)[4]) {
+  Prim p;
+  const double rinv = rcp_nr(U[0]);
+  p.u = U[1] * rinv;
+  p.v = U[2] * rinv;
+  p.q2 = p.u * p.u + p.v * p.v;
+  const double pr = gm1 * (U[3] - 0.5 * U[0] * p.q2);
+  const double c2 = (gm1 + 1.0) * pr * rinv;
+  p.c = sqrt(c2);
+  p.ci = rcp_nr(p.c);
+  p.H = (U[3] + pr) * rinv;
+  p.b1 = gm1 * rcp_nr(c2);
+  p.b2 = 0.5 * p.b1 * p.q2;
+  return p;
 }
 
-// y-sweep outputs (y-edges, interior g, w^)
-template <int EQ, int NC, class TR>
-__device__ __forceinline__ void eval_y_sweep(const SchemeParams& P, const TR (&Cc)[NC][15],
-                                             CellRecon<NC, TR>& R, bool interior) {
-  if (interior) {
-#pragma unroll
-    for (int k = 0; k < NC; ++k) R.volg[k] = (TR)0;
-  }
-#pragma unroll
-  for (int G = 0; G < 3; ++G) {
-    const TR e = (TR)(G == 0 ? -G3S : (G == 1 ? 0.0 : G3S));
-    TR in[3][NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      TR d[5];
-      restrict_xi<TR>(Cc[k], e, d);
-      TR em, ep, gm, g0, gp;
-      eval5<TR>(d, em, ep, gm, g0, gp);
-      R.ym[G][k] = em;
-      R.yp[G][k] = ep;
-      in[0][k] = gm;
-      in[1][k] = g0;
-      in[2][k] = gp;
-    }
-    if (interior) {
-#pragma unroll
-      for (int H = 0; H < 3; ++H) {
-        TR g[NC];
-        phys_flux<EQ, NC, 1, TR>(P, in[H], g);
-        const TR wgt = (TR)(g3w(G) * g3w(H));
-#pragma unroll
-        for (int k = 0; k < NC; ++k) R.volg[k] += wgt * g[k];
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NC; ++k) R.wh[k] = qw_2d<TR>(Cc[k]);
-}
-
-// characteristic sweep: project conserved p0 coefficients with L, weight
-// per characteristic field, back-project the combined polynomial with R
-template <int DIR, class TR>
-__device__ __forceinline__ void char_sweep(const SchemeParams& P, const double (&c)[4][15],
-                                           const double (&u5)[4], const double (&dL)[4],
-                                           const double (&dR)[4], const double (&dB)[4],
-                                           const double (&dT)[4], TR (&Cc)[4][15]) {
-  double L[4][4], R[4][4];
-  euler_eig<4, DIR>(P.gas_gamma - 1.0, u5, L, R);
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int n = 0; n < 15; ++n) Cc[k][n] = (TR)0;
-#pragma unroll
-  for (int ch = 0; ch < 4; ++ch) {
-    double cc[15];
-#pragma unroll
-    for (int n = 0; n < 15; ++n) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) s += L[ch][k] * c[k][n];
-      cc[n] = s;
-    }
-    double w5 = 0, wL = 0, wR = 0, wB = 0, wT = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      w5 += L[ch][k] * u5[k];
-      wL += L[ch][k] * dL[k];
-      wR += L[ch][k] * dR[k];
-      wB += L[ch][k] * dB[k];
-      wT += L[ch][k] * dT[k];
-    }
-    const double asum = fabs(w5 - wB) + fabs(w5 - wL) + fabs(w5) + fabs(w5 + wR) + fabs(w5 + wT);
-    TR C[15];
-    hweno_2d<TR>(P, cc, w5, wL, wR, wB, wT, asum, C);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const TR r = (TR)R[k][ch];
-#pragma unroll
-      for (int n = 0; n < 15; ++n) Cc[k][n] += r * C[n];
-    }
-  }
-}
-
-// Reconstruct cell (i, j).  need_x: x-edge values, f and v^ are needed.
-template <int EQ, bool CHAR, class TR, class TM>
-__device__ __forceinline__ void reconstruct_cell(const StageArgs<TM>& A, const InstDev& I, int i,
-                                                 int j, bool need_x,
-                                                 CellRecon<(EQ == EQ_EULER ? 4 : 1), TR>& R) {
-  constexpr int NC = EQ == EQ_EULER ? 4 : 1;
-  const SchemeParams& P = A.P;
-  Sten2 S[NC];
-  load_stencil<NC, TM>(A, I, i, j, S);
-  double c[NC][15], u5[NC], dL[NC], dR[NC], dB[NC], dT[NC];
-#pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    p0_coeffs_2d(S[k], c[k]);
-    u5[k] = S[k].u[4];
-    dL[k] = S[k].u[4] - S[k].u[3];
-    dR[k] = S[k].u[5] - S[k].u[4];
-    dB[k] = S[k].u[4] - S[k].u[1];
-    dT[k] = S[k].u[7] - S[k].u[4];
-    R.u5[k] = u5[k];
-  }
-  if constexpr (EQ == EQ_EULER && CHAR) {
-    TR Cc[4][15];
-    if (need_x) {
-      char_sweep<0, TR>(P, c, u5, dL, dR, dB, dT, Cc);
-      eval_x_sweep<EQ, 4, TR>(P, Cc, R, false);
-    }
-    char_sweep<1, TR>(P, c, u5, dL, dR, dB, dT, Cc);
-    eval_y_sweep<EQ, 4, TR>(P, Cc, R, need_x);
+// Row k of the left eigenvectors and column k of the right eigenvectors of
+// the Euler flux Jacobian in direction DIR (ideal gas):
+// x: R = [(1,u-c,v,H-uc), (1,u,v,q^2/2), (0,0,1,v), (1,u+c,v,H+uc)]
+// y: R = [(1,u,v-c,H-vc), (1,u,v,q^2/2), (0,1,0,u), (1,u,v+c,H+vc)]
+template <int DIR>
+__device__ __forceinline__ void eig_row(const Prim& p, int k, double (&l)[4], double (&r)[4]) {
+  const double un = DIR == 0 ? p.u : p.v;  // normal velocity
+  const double ut = DIR == 0 ? p.v : p.u;  // tangential velocity
+  const int n = DIR == 0 ? 1 : 2, t = DIR == 0 ? 2 : 1;
+  double ll[4], rr[4];
+  if (k == 0 || k == 3) {
+    const double s = k == 0 ? 1.0 : -1.0;
+    ll[0] = 0.5 * (p.b2 + s * un * p.ci);
+    ll[n] = -0.5 * (p.b1 * un + s * p.ci);
+    ll[t] = -0.5 * p.b1 * ut;
+    ll[3] = 0.5 * p.b1;
+    rr[0] = 1.0;
+    rr[n] = un - s * p.c;
+    rr[t] = ut;
+    rr[3] = p.H - s * un * p.c;
+  } else if (k == 1) {
+    ll[0] = 1.0 - p.b2;
+    ll[n] = p.b1 * un;
+    ll[t] = p.b1 * ut;
+    ll[3] = -p.b1;
+    rr[0] = 1.0;
+    rr[n] = un;
+    rr[t] = ut;
+    rr[3] = 0.5 * p.q2;
   } else {
-    TR Cc[NC][15];
+    ll[0] = -ut;
+    ll[n] = 0.0;
+    ll[t] = 1.0;
+    ll[3] = 0.0;
+    rr[0] = 0.0;
+    rr[n] = 0.0;
+    rr[t] = 1.0;
+    rr[3] = ut;
+  }
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const double asum = fabs(S[k].u[1]) + fabs(S[k].u[3]) + fabs(S[k].u[4]) + fabs(S[k].u[5]) +
-                          fabs(S[k].u[7]);
-      hweno_2d<TR>(P, c[k], u5[k], dL[k], dR[k], dB[k], dT[k], asum, Cc[k]);
+  for (int m = 0; m < 4; ++m) {
+    l[m] = ll[m];
+    r[m] = rr[m];
+  }
+}
+
+template <int NC, class TM>
+struct RowBuf {
+  double u[3][NC][kCols];      // cell averages of three rows
+  double m[3][2][NC][kCols];   // x and y moments of three rows (widened once on store)
+};
+
+// The 17 stencil values of field/component data around lane column `l`
+// (LDS columns l, l+1, l+2; ring slots sb, sc, st for rows j-1, j, j+1).
+template <int NC, class TM>
+__device__ __forceinline__ void read_stencil(const RowBuf<NC, TM>& B, int sb, int sc, int st, int l,
+                                             int k, Sten2& S) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    S.u[a] = B.u[sb][k][l + a];
+    S.u[3 + a] = B.u[sc][k][l + a];
+    S.u[6 + a] = B.u[st][k][l + a];
+  }
+  S.v[0] = B.m[sb][0][k][l + 1];
+  S.v[1] = B.m[sc][0][k][l];
+  S.v[2] = B.m[sc][0][k][l + 2];
+  S.v[3] = B.m[st][0][k][l + 1];
+  S.w[0] = B.m[sb][1][k][l + 1];
+  S.w[1] = B.m[sc][1][k][l];
+  S.w[2] = B.m[sc][1][k][l + 2];
+  S.w[3] = B.m[st][1][k][l + 1];
+}
+
+// Scalar HWENO reconstruction of one stencil -> combined coefficients
+template <class TR>
+__device__ __forceinline__ void recon_scalar(const SchemeParams& P, const Sten2& S, TR (&C)[15]) {
+  double c[15];
+  p0_coeffs_2d(S, c);
+  const double u5 = S.u[4];
+  const double asum = fabs(S.u[1]) + fabs(S.u[3]) + fabs(u5) + fabs(S.u[5]) + fabs(S.u[7]);
+  hweno_2d<TR>(P, c, u5, u5 - S.u[3], S.u[5] - u5, u5 - S.u[1], S.u[7] - u5, asum, C);
+}
+
+// Characteristic sweep in direction DIR: combined polynomials of the four
+// fields mapped back to conserved variables, Cc[m][n].
+template <int DIR, class TR, class TM>
+__device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr,
+                                           const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
+                                           TR (&Cc)[4][15]) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 15; ++n) Cc[m][n] = (TR)0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double lrow[4], rcol[4];
+    eig_row<DIR>(pr, k, lrow, rcol);
+    Sten2 W;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) W.u[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) W.v[q] = W.w[q] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      Sten2 S;
+      read_stencil<4, TM>(B, sb, sc, st, l, m, S);
+      const double lm = lrow[m];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) W.u[q] += lm * S.u[q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        W.v[q] += lm * S.v[q];
+        W.w[q] += lm * S.w[q];
+      }
     }
-    // one reconstruction: the interior values serve both f and g
-    if (need_x) eval_x_sweep<EQ, NC, TR>(P, Cc, R, true);
-    eval_y_sweep<EQ, NC, TR>(P, Cc, R, false);
+    TR C[15];
+    recon_scalar<TR>(P, W, C);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const TR r = (TR)rcol[m];
+#pragma unroll
+      for (int n = 0; n < 15; ++n) Cc[m][n] += r * C[n];
+    }
   }
 }
 
 template <int EQ, bool CHAR, class TR, class TM>
-__global__ __launch_bounds__(64) void stage2d_kernel(const StageArgs<TM> A) {
+__global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 4 : 1;
-  const int lane = threadIdx.x & 63;
+  __shared__ RowBuf<NC, TM> B;
+  const int lane = threadIdx.x;
   const int w = blockIdx.x;
   if (w >= A.n_waves) return;
   const SchemeParams& P = A.P;
@@ -253,61 +196,178 @@ __global__ __launch_bounds__(64) void stage2d_kernel(const StageArgs<TM> A) {
   if (A.stage == 1) { ra = 0.75; rb = 0.25; }
   if (A.stage == 2) { ra = 1.0 / 3.0; rb = 2.0 / 3.0; }
   const long long plane = A.plane;
-  const TR gxs[3] = {(TR)(-G3S), (TR)0, (TR)G3S};
+  const double gm1 = P.gas_gamma - 1.0;
 
   for (int it = A.work_ptr[w]; it < A.work_ptr[w + 1]; ++it) {
     const WorkItem wk = A.work[it];
     if (A.done != nullptr && A.done[wk.inst]) continue;
     const InstDev I = A.inst[wk.inst];
-    int i = wk.a * kStripWidth - 1 + lane;
-    if (i > I.nx) i = I.nx;
-    const bool col_owner = lane >= 1 && lane <= kStripWidth && i < I.nx;
+    const int nx = I.nx, ny = I.ny;
+    const int c0 = wk.a * kStripWidth;
+    int i = c0 - 1 + lane;
+    if (i > nx) i = nx;
+    const bool col_owner = lane >= 1 && lane <= kStripWidth && i < nx;
     const TR a1 = (TR)A.alpha[2 * wk.inst], a2 = (TR)A.alpha[2 * wk.inst + 1];
     const double dt = A.dt[wk.inst];
     const double idx = 1.0 / I.dx, idy = 1.0 / I.dy;
     const int r0 = wk.b, r1 = wk.c;
+    const double* u_in = A.u_in + I.offset;
+    const TM* m_in = A.m_in + I.offset;
 
-    // carried from the row below: its upper y-edge values, its pending RHS,
-    // its modified moments and its cell average
+    // grid columns of the LDS columns this lane loads (clamped, then wrapped)
+    const int gx0 = wrap_index(min(c0 - 2 + lane, nx + 1), nx, I.bc[0], I.bc[1]);
+    const int gx1 = wrap_index(min(c0 + 62 + lane, nx + 1), nx, I.bc[0], I.bc[1]);
+    const bool extra = lane < 2;
+
+    // register prefetch of one row (this lane's column and, for lanes 0-1,
+    // one of the two extra columns)
+    double pu0[NC], pu1[NC];
+    TM pm0[2][NC], pm1[2][NC];
+    auto fetch = [&](int row) {
+      const long long base = (long long)wrap_index(row, ny, I.bc[2], I.bc[3]) * nx;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        pu0[k] = u_in[k * plane + base + gx0];
+        pm0[0][k] = m_in[k * plane + base + gx0];
+        pm0[1][k] = m_in[(NC + k) * plane + base + gx0];
+        if (extra) {
+          pu1[k] = u_in[k * plane + base + gx1];
+          pm1[0][k] = m_in[k * plane + base + gx1];
+          pm1[1][k] = m_in[(NC + k) * plane + base + gx1];
+        }
+      }
+    };
+    auto store = [&](int slot) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        B.u[slot][k][lane] = pu0[k];
+        B.m[slot][0][k][lane] = (double)pm0[0][k];
+        B.m[slot][1][k][lane] = (double)pm0[1][k];
+        if (extra) {
+          B.u[slot][k][64 + lane] = pu1[k];
+          B.m[slot][0][k][64 + lane] = (double)pm1[0][k];
+          B.m[slot][1][k][64 + lane] = (double)pm1[1][k];
+        }
+      }
+    };
+    auto slot_of = [](int row) { return ((row % 3) + 3) % 3; };
+
+    __syncthreads();  // the previous item's reads of B are complete
+    // prologue: rows r0-2 .. r0 into LDS, r0+1 into registers
+    for (int row = r0 - 2; row <= r0; ++row) {
+      fetch(row);
+      store(slot_of(row));
+    }
+    fetch(r0 + 1);
+    __syncthreads();
+
+    // state carried from the row below (pending right-hand side of row j-1)
     TR yprev[3][NC];
     double F1p[NC];
     TR F2p[NC], F3p[NC], vhp[NC], whp[NC];
-    double u5p[NC];
     double amax_x = 0.0, amax_y = 0.0;
     bool ok = true;
 
     for (int j = r0 - 1; j <= r1; ++j) {
       const bool row_out = j >= r0 && j < r1;
-      CellRecon<NC, TR> R;
-      reconstruct_cell<EQ, CHAR, TR, TM>(A, I, i, j, row_out, R);
+      const int sb = slot_of(j - 1), sc = slot_of(j), st = slot_of(j + 1);
 
-      // y-flux at y_{j-1/2}: u- = row below at eta=+1/2, u+ = this row at -1/2
-      TR gb[3][NC];
-      if (j >= r0) {
+      // ---- reconstruction of row j, y-direction ----
+      TR Cc[NC][15];
+      Prim pr;
+      if constexpr (EQ == EQ_EULER && CHAR) {
+        double U5[4];
 #pragma unroll
-        for (int G = 0; G < 3; ++G) lf_flux<EQ, NC, 1, TR>(P, yprev[G], R.ym[G], a2, gb[G]);
-      }
-      // finish the row below
-      if (j - 1 >= r0 && j - 1 < r1) {
+        for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
+        pr = make_prim(gm1, U5);
+        char_sweep<1, TR, TM>(P, pr, B, sb, sc, st, lane, Cc);
+      } else {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-          TR s = (TR)0, sm = (TR)0;
-#pragma unroll
-          for (int G = 0; G < 3; ++G) {
-            s += (TR)g3w(G) * gb[G][k];
-            sm += (TR)g3w(G) * gxs[G] * gb[G][k];
-          }
-          F1p[k] -= (double)s * idy;
-          F2p[k] -= sm * (TR)idy;
-          F3p[k] -= s * (TR)(0.5 * idy);
+          Sten2 S;
+          read_stencil<NC, TM>(B, sb, sc, st, lane, k, S);
+          recon_scalar<TR>(P, S, Cc[k]);
         }
+      }
+      // y-edges at (xi_G, -+1/2), interior values for g (and f when the
+      // reconstruction is shared), y-fluxes at y_{j-1/2}
+      TR F1n_s[NC], F2n[NC], F3n[NC];  // new row: bottom-flux terms
+      double F1n[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        F1n[k] = 0.0;
+        F2n[k] = (TR)0;
+        F3n[k] = (TR)0;
+        F1n_s[k] = (TR)0;
+      }
+      TR volf[NC], volg[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) volf[k] = volg[k] = (TR)0;
+#pragma unroll
+      for (int G = 0; G < 3; ++G) {
+        const TR xg = (TR)g3x(G);
+        TR ym[NC], yp[NC], in[3][NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          TR d[5];
+          restrict_xi<TR>(Cc[k], xg, d);
+          eval5<TR>(d, ym[k], yp[k], in[0][k], in[1][k], in[2][k]);
+        }
+        if (row_out) {
+#pragma unroll
+          for (int H = 0; H < 3; ++H) {
+            const TR wgt = (TR)(g3w(G) * g3w(H));
+            TR g[NC];
+            phys_flux<EQ, NC, 1, TR>(P, in[H], g);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) volg[k] += wgt * g[k];
+            if constexpr (!(EQ == EQ_EULER && CHAR)) {
+              TR f[NC];
+              phys_flux<EQ, NC, 0, TR>(P, in[H], f);
+#pragma unroll
+              for (int k = 0; k < NC; ++k) volf[k] += wgt * f[k];
+            }
+          }
+        }
+        if (j >= r0) {
+          // u- = row below at eta = +1/2, u+ = this row at eta = -1/2
+          TR gb[NC];
+          lf_flux<EQ, NC, 1, TR>(P, yprev[G], ym, a2, gb);
+          const TR wg = (TR)g3w(G);
+#pragma unroll
+          for (int k = 0; k < NC; ++k) {
+            F1n_s[k] += wg * gb[k];       // sum_G w_G g_{G,j-1/2}
+            F2n[k] += wg * xg * gb[k];    // sum_G w_G xi_G g_{G,j-1/2}
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) yprev[G][k] = yp[k];
+      }
+      if (j >= r0) {
+        // the same sums close row j-1 (upper edge) and open row j (lower edge)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          F1p[k] -= (double)F1n_s[k] * idy;
+          F2p[k] -= F2n[k] * (TR)idy;
+          F3p[k] -= F1n_s[k] * (TR)(0.5 * idy);
+          F3n[k] = -F1n_s[k] * (TR)(0.5 * idy);
+          F2n[k] = F2n[k] * (TR)idy;
+        }
+      }
+      TR whn[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) whn[k] = qw_2d<TR>(Cc[k]);
+
+      // ---- row j-1 is complete: Runge-Kutta update and store ----
+      if (j - 1 >= r0 && j - 1 < r1) {
         if (col_owner) {
-          const long long o = I.offset + (long long)(j - 1) * I.nx + i;
+          const long long o = I.offset + (long long)(j - 1) * nx + i;
           double Uo[NC];
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
+            const double uin = B.u[sb][k][lane + 1];
             const double ub = A.stage == 0 ? 0.0 : A.u_base[k * plane + o];
-            const double un = ra * ub + rb * (u5p[k] + dt * F1p[k]);
+            const double un = ra * ub + rb * (uin + dt * F1p[k]);
             TR vn, wn;
             if (A.stage == 0) {
               A.m_base[k * plane + o] = (TM)vhp[k];
@@ -331,53 +391,68 @@ __global__ __launch_bounds__(64) void stage2d_kernel(const StageArgs<TM> A) {
           amax_y = fmax(amax_y, sy);
         }
       }
+
       if (row_out) {
-        // x-fluxes of this row at the 3 Gauss points of each x-edge
-        TR F2x[NC], F3x[NC];
+        // ---- x-direction reconstruction of row j ----
+        if constexpr (EQ == EQ_EULER && CHAR) char_sweep<0, TR, TM>(P, pr, B, sb, sc, st, lane, Cc);
         double F1x[NC];
+        TR F2x[NC], F3x[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
           F1x[k] = 0.0;
-          F2x[k] = (TR)0;
-          F3x[k] = (TR)0;
+          F2x[k] = F3x[k] = (TR)0;
         }
 #pragma unroll
-        for (int G = 0; G < 3; ++G) {
+        for (int H = 0; H < 3; ++H) {
+          const TR yh = (TR)g3x(H);
+          TR xm[NC], xp[NC], in[3][NC];
+#pragma unroll
+          for (int k = 0; k < NC; ++k) {
+            TR d[5];
+            restrict_eta<TR>(Cc[k], yh, d);
+            eval5<TR>(d, xm[k], xp[k], in[0][k], in[1][k], in[2][k]);
+          }
+          if constexpr (EQ == EQ_EULER && CHAR) {
+#pragma unroll
+            for (int G = 0; G < 3; ++G) {
+              TR f[NC];
+              phys_flux<EQ, NC, 0, TR>(P, in[G], f);
+              const TR wgt = (TR)(g3w(G) * g3w(H));
+#pragma unroll
+              for (int k = 0; k < NC; ++k) volf[k] += wgt * f[k];
+            }
+          }
+          // x_{i-1/2} at eta_H: u- = left lane at +1/2, u+ = this lane at -1/2
           TR um[NC], fl[NC], fr[NC];
 #pragma unroll
-          for (int k = 0; k < NC; ++k) um[k] = __shfl_up(R.xp[G][k], 1, 64);
-          lf_flux<EQ, NC, 0, TR>(P, um, R.xm[G], a1, fl);
+          for (int k = 0; k < NC; ++k) um[k] = __shfl_up(xp[k], 1, 64);
+          lf_flux<EQ, NC, 0, TR>(P, um, xm, a1, fl);
 #pragma unroll
           for (int k = 0; k < NC; ++k) fr[k] = __shfl_down(fl[k], 1, 64);
-          const TR wg = (TR)g3w(G);
+          const TR wg = (TR)g3w(H);
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             F1x[k] += (double)wg * ((double)fr[k] - (double)fl[k]);
             F2x[k] += wg * (fl[k] + fr[k]);
-            F3x[k] += wg * gxs[G] * (fr[k] - fl[k]);
+            F3x[k] += wg * yh * (fr[k] - fl[k]);
           }
         }
-        // pending RHS of this row: x-terms, volume terms, lower y-flux
+        // pending right-hand side of row j
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-          TR s = (TR)0, sm = (TR)0;
-#pragma unroll
-          for (int G = 0; G < 3; ++G) {
-            s += (TR)g3w(G) * gb[G][k];
-            sm += (TR)g3w(G) * gxs[G] * gb[G][k];
-          }
-          F1p[k] = -F1x[k] * idx + (double)s * idy;
-          F2p[k] = -F2x[k] * (TR)(0.5 * idx) + R.volf[k] * (TR)idx + sm * (TR)idy;
-          F3p[k] = -F3x[k] * (TR)idx + R.volg[k] * (TR)idy - s * (TR)(0.5 * idy);
-          vhp[k] = R.vh[k];
-          whp[k] = R.wh[k];
-          u5p[k] = R.u5[k];
+          F1p[k] = -F1x[k] * idx + (double)F1n_s[k] * idy;
+          F2p[k] = -F2x[k] * (TR)(0.5 * idx) + volf[k] * (TR)idx + F2n[k];
+          F3p[k] = -F3x[k] * (TR)idx + volg[k] * (TR)idy + F3n[k];
+          vhp[k] = qv_2d<TR>(Cc[k]);
+          whp[k] = whn[k];
         }
       }
-#pragma unroll
-      for (int G = 0; G < 3; ++G)
-#pragma unroll
-        for (int k = 0; k < NC; ++k) yprev[G][k] = R.yp[G][k];
+
+      // ---- advance the LDS ring: row j+2 from registers, prefetch j+3 ----
+      __syncthreads();
+      if (j + 2 <= r1 + 1) store(slot_of(j + 2));
+      if (j + 3 <= r1 + 1) fetch(j + 3);
+      __syncthreads();
     }
     if (!ok) atomicOr(A.status, 1);
     if (A.alpha_next != nullptr) {
