@@ -107,7 +107,16 @@ void free_handle(hwenou_handle* h) {
 int build_work(hwenou_handle* h) {
   std::vector<WorkItem> items;
   std::vector<int> ptr;
-  const int wpc = h->waves_per_cu > 0 ? h->waves_per_cu : (h->dim == 1 ? 8 : 2);
+  // default: as many waves per compute unit as can be resident at once
+  int wpc = h->waves_per_cu;
+  if (wpc <= 0) {
+    const bool chr = h->desc.eq == HWENOU_EQ_EULER && h->desc.char_decomp;
+    if (h->dim == 1)
+      wpc = 4 * occupancy_stage_1d(h->desc.eq, chr, h->mixed, 256);
+    else
+      wpc = occupancy_stage_2d(h->desc.eq, chr, h->mixed, 64);
+    if (wpc <= 0) wpc = 4;
+  }
   const long long target_waves = (long long)h->n_cu * wpc;
   if (h->dim == 1) {
     std::vector<WorkItem> tiles;

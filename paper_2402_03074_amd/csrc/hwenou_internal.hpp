@@ -55,6 +55,10 @@ hipError_t launch_stage_1d(int eq, bool char_decomp, bool mixed, const void* arg
 hipError_t launch_stage_2d(int eq, bool char_decomp, bool mixed, const void* args, int blocks,
                            int threads, hipStream_t s);
 
+// resident blocks per compute unit of a stage kernel at `threads` per block
+int occupancy_stage_1d(int eq, bool char_decomp, bool mixed, int threads);
+int occupancy_stage_2d(int eq, bool char_decomp, bool mixed, int threads);
+
 // auxiliary kernels
 struct AuxArgs {
   SchemeParams P;

@@ -492,4 +492,32 @@ hipError_t launch_stage_2d(int eq, bool char_decomp, bool mixed, const void* arg
   }
 }
 
+template <int EQ, bool CHAR, class TR, class TM>
+static int occupancy(int threads) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stage2d_kernel<EQ, CHAR, TR, TM>, threads, 0) !=
+      hipSuccess)
+    return 0;
+  return blocks;
+}
+
+int occupancy_stage_2d(int eq, bool char_decomp, bool mixed, int threads) {
+  if (mixed) {
+    switch (eq) {
+      case EQ_ADVECTION: return occupancy<EQ_ADVECTION, false, float, float>(threads);
+      case EQ_BURGERS: return occupancy<EQ_BURGERS, false, float, float>(threads);
+      default:
+        return char_decomp ? occupancy<EQ_EULER, true, float, float>(threads)
+                           : occupancy<EQ_EULER, false, float, float>(threads);
+    }
+  }
+  switch (eq) {
+    case EQ_ADVECTION: return occupancy<EQ_ADVECTION, false, double, double>(threads);
+    case EQ_BURGERS: return occupancy<EQ_BURGERS, false, double, double>(threads);
+    default:
+      return char_decomp ? occupancy<EQ_EULER, true, double, double>(threads)
+                         : occupancy<EQ_EULER, false, double, double>(threads);
+  }
+}
+
 }  // namespace hwenou
