@@ -46,14 +46,18 @@ def parse():
     p.add_argument("--size", type=int, default=2048)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--precisions", default="mixed,fp64")
+    p.add_argument("--tune", action="store_true",
+                   help="run the launch-shape autotuner first (default: the library's "
+                        "occupancy-based launch shape)")
     return p.parse_args()
 
 
-def run_precision(H, torch, u0, m0, n, precision, steps, warmup):
+def run_precision(H, torch, u0, m0, n, precision, steps, warmup, tune):
     inst = H.make_inst(n, n, (0.0, 10.0, 0.0, 10.0), "periodic")
     S = H.Solver(2, "euler", [inst], precision=precision)
     ug = torch.tensor(u0.reshape(4, -1), device="cuda")
     mg = torch.tensor(m0.reshape(2, 4, -1), device="cuda").to(S.mom_dtype)
+    launch = S.autotune(ug, mg) if tune else None
     # warm-up steps (untimed), then exactly `steps` timed steps
     if warmup > 0:
         S.advance(ug, mg, 0.6, 1e30, warmup)
@@ -99,10 +103,10 @@ def run_precision(H, torch, u0, m0, n, precision, steps, warmup):
     del ug, mg, u1, m1, u2, m2, u3, m3
     torch.cuda.empty_cache()
     return {"wall_s": wall, "event_ms": ev_ms, "stage_ms": stage_ms, "state": out,
-            "t": tg[0], "status": status}
+            "t": tg[0], "status": status, "launch": launch}
 
 
-def copy_calibration(torch, mib=256):
+def copy_calibration(torch, mib=1024):
     """A plain device-to-device copy of known size, outside the timed region:
     its FETCH_SIZE / WRITE_SIZE counters calibrate the HBM-traffic counters of
     the stage kernel."""
@@ -153,7 +157,8 @@ def main():
     for prec in args.precisions.split(","):
         print(f"[bench] {prec}: {args.warmup} warm-up + {args.steps} timed steps",
               file=sys.stderr, flush=True)
-        results[prec] = run_precision(H, torch, u0, m0, n, prec, args.steps, args.warmup)
+        results[prec] = run_precision(H, torch, u0, m0, n, prec, args.steps, args.warmup,
+                                      args.tune)
         r = results[prec]
         print(f"[bench] {prec}: {r['event_ms'] / args.steps:.3f} ms/step, stages "
               f"{[round(x, 3) for x in r['stage_ms']]} ms", file=sys.stderr, flush=True)
@@ -205,6 +210,7 @@ def main():
             "rel_linf_rho_diff": float(np.abs(a[0] - b[0]).max() / np.abs(b[0]).max()),
             "after_steps": args.warmup + args.steps}
     line["status"] = {p: results[p]["status"] for p in results}
+    line["launch"] = {p: results[p]["launch"] for p in results}
     line["copy_calibration_mib"] = copy_calibration(torch)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

@@ -144,6 +144,14 @@ int hwenou_status(hwenou_handle* h);
  * the autotuner; takes effect on the next call. */
 int hwenou_set_launch(hwenou_handle* h, int waves_per_cu, int rows_per_item);
 
+/* Autotuner of the persistent launch shape: times stage 0 on (ubar, mom)
+ * (read only; output goes to handle scratch) for candidate waves per
+ * compute unit (multiples of the resident count) and, in 2D, rows per work
+ * item; keeps the fastest (median of `reps` timed launches) and returns it.
+ * Synchronous.  Errors: EINVAL, EHIP. */
+int hwenou_autotune(hwenou_handle* h, const double* ubar, const void* mom, int reps,
+                    int* waves_per_cu, int* rows_per_item);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,8 @@ WEIGHTS = {"scale_invariant": 0, "zq": 1, "linear": 2}
 BC = {"periodic": 0, "transmissive": 1}
 
 EXPORTS = ["hwenou_create", "hwenou_destroy", "hwenou_strerror", "hwenou_max_wavespeed",
-           "hwenou_stage", "hwenou_advance", "hwenou_status", "hwenou_set_launch"]
+           "hwenou_stage", "hwenou_advance", "hwenou_status", "hwenou_set_launch",
+           "hwenou_autotune"]
 
 
 class HwenouError(RuntimeError):
@@ -77,6 +78,7 @@ def lib():
                                  C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.hwenou_status.argtypes = [vp]
     L.hwenou_set_launch.argtypes = [vp, C.c_int, C.c_int]
+    L.hwenou_autotune.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     for name in EXPORTS:
         getattr(L, name).restype = C.c_char_p if name == "hwenou_strerror" else C.c_int
     _lib = L
@@ -175,6 +177,13 @@ def hwenou_set_launch(h, waves_per_cu, rows_per_item=0):
            "hwenou_set_launch")
 
 
+def hwenou_autotune(h, ubar, mom, reps=3):
+    w, r = C.c_int(), C.c_int()
+    _check(lib().hwenou_autotune(h, _ptr(ubar), _ptr(mom), int(reps), C.byref(w), C.byref(r)),
+           "hwenou_autotune")
+    return w.value, r.value
+
+
 class Solver:
     """Owns one handle; state arrays are torch tensors on the GPU.
 
@@ -221,6 +230,11 @@ class Solver:
 
     def set_launch(self, waves_per_cu, rows_per_item=0):
         hwenou_set_launch(self.h, waves_per_cu, rows_per_item)
+
+    def autotune(self, ubar, mom, reps=3, cache=True):
+        """Pick the launch shape for this handle (see autotune.py)."""
+        from . import autotune
+        return autotune.tune(self, ubar, mom, reps=reps, use_cache=cache)
 
     def close(self):
         if self.h is not None:

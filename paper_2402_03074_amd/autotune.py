@@ -1,0 +1,61 @@
+"""Launch-shape autotuner with a persistent cache.
+
+The library's hwenou_autotune times the persistent stage launch for
+candidate waves per compute unit and (2D) rows per work item.  This module
+keys the winner by device architecture, scheme (dim, equation, precision,
+characteristic decomposition), the total cell count rounded to a power of two
+and the instance count rounded likewise, and stores it in a JSON file, so
+later handles of the same class reuse it without timing.
+
+Cache file: $HWENOU_TUNE_CACHE, else ~/.cache/hwenou/autotune.json.
+"""
+import json
+import math
+import os
+
+from . import hwenou_autotune, hwenou_set_launch
+
+
+def cache_path():
+    return os.environ.get("HWENOU_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "hwenou",
+                                       "autotune.json"))
+
+
+def _key(solver):
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    d = solver.desc
+    cells = max(1, int(solver.plane))
+    return "|".join(str(x) for x in (arch, d.dim, d.eq, d.precision, d.char_decomp,
+                                      int(math.log2(cells)),
+                                      int(math.log2(max(1, solver.n_inst)))))
+
+
+def _load(path):
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune(solver, ubar, mom, reps=3, use_cache=True):
+    """Set the best launch shape on `solver`; returns (waves_per_cu, rows)."""
+    path = cache_path()
+    key = _key(solver)
+    table = _load(path) if use_cache else {}
+    if key in table:
+        w, r = table[key]
+        hwenou_set_launch(solver.h, w, r)
+        return w, r
+    w, r = hwenou_autotune(solver.h, ubar, mom, reps)
+    if use_cache:
+        table = _load(path)
+        table[key] = [w, r]
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return w, r

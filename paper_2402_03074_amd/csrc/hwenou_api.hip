@@ -418,6 +418,75 @@ int hwenou_set_launch(hwenou_handle* h, int waves_per_cu, int rows_per_item) {
   return HWENOU_OK;
 }
 
+int hwenou_autotune(hwenou_handle* h, const double* ubar, const void* mom, int reps,
+                    int* waves_per_cu, int* rows_per_item) {
+  if (!h || !ubar || !mom || reps < 1 || !aligned(ubar, 8) || !aligned(mom, h->mom_elem))
+    return HWENOU_EINVAL;
+  const bool chr = h->desc.eq == HWENOU_EQ_EULER && h->desc.char_decomp;
+  const int occ = h->dim == 1 ? 4 * occupancy_stage_1d(h->desc.eq, chr, h->mixed, 256)
+                              : occupancy_stage_2d(h->desc.eq, chr, h->mixed, 64);
+  const int base = occ > 0 ? occ : 4;
+  std::vector<int> wpcs;
+  for (int f : {1, 2, 4}) {
+    const int w = std::min(32, base * f);
+    if (std::find(wpcs.begin(), wpcs.end(), w) == wpcs.end()) wpcs.push_back(w);
+  }
+  if (base > 1) wpcs.push_back(std::max(1, base / 2));
+  std::vector<int> rows = h->dim == 1 ? std::vector<int>{0} : std::vector<int>{0, 16, 32, 64};
+  hipStream_t st = h->own;
+  HIPCHK(hipEventRecord(h->ev_in, h->stream));
+  HIPCHK(hipStreamWaitEvent(st, h->ev_in, 0));
+  HIPCHK(hipMemsetAsync(h->d_dt, 0, h->n_inst * sizeof(double), st));
+  AuxArgs a = aux_args(h, ubar, 1.0, 0.0, 0);
+  hipError_t e = launch_max_wavespeed(a, st);
+  if (e != hipSuccess) return hip_fail(e, "max_wavespeed launch");
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  const int save_w = h->waves_per_cu, save_r = h->rows_per_item;
+  float best = 1e30f;
+  int bw = save_w, br = save_r;
+  int rc = HWENOU_OK;
+  for (int w : wpcs) {
+    for (int r : rows) {
+      h->waves_per_cu = w;
+      h->rows_per_item = r;
+      h->work_dirty = true;
+      if ((rc = build_work(h))) break;
+      std::vector<float> ts;
+      for (int k = 0; k <= reps && !rc; ++k) {  // first launch warms up
+        if (hipEventRecord(t0, st) != hipSuccess) rc = HWENOU_EHIP;
+        if (!rc) rc = launch_stage(h, 0, h->d_dt, h->d_alpha, nullptr, ubar, mom, h->s1u, h->s1m,
+                                   nullptr, st);
+        if (!rc && hipEventRecord(t1, st) != hipSuccess) rc = HWENOU_EHIP;
+        if (!rc && hipEventSynchronize(t1) != hipSuccess) rc = HWENOU_EHIP;
+        float ms = 0.f;
+        if (!rc && hipEventElapsedTime(&ms, t0, t1) != hipSuccess) rc = HWENOU_EHIP;
+        if (!rc && k > 0) ts.push_back(ms);
+      }
+      if (rc) break;
+      std::sort(ts.begin(), ts.end());
+      const float med = ts[ts.size() / 2];
+      if (med < best) {
+        best = med;
+        bw = w;
+        br = r;
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  h->waves_per_cu = rc ? save_w : bw;
+  h->rows_per_item = rc ? save_r : br;
+  h->work_dirty = true;
+  if (rc) return rc == HWENOU_EHIP ? hip_fail(hipGetLastError(), "autotune timing") : rc;
+  HIPCHK(hipStreamSynchronize(st));
+  if (waves_per_cu) *waves_per_cu = bw;
+  if (rows_per_item) *rows_per_item = br;
+  return HWENOU_OK;
+}
+
 int hwenou_max_wavespeed(hwenou_handle* h, const double* ubar, double* alpha_dev) {
   if (!h || !ubar || !alpha_dev || !aligned(ubar, 8) || !aligned(alpha_dev, 8))
     return HWENOU_EINVAL;

@@ -211,3 +211,24 @@ def test_stage_api_rejects_stage1_before_stage0():
     with pytest.raises(H.HwenouError):
         S.stage(0, dt, al, u, m, u, m)  # aliasing in and out
     S.close()
+
+
+def test_autotuner_keeps_results_bitwise(tmp_path, monkeypatch):
+    monkeypatch.setenv("HWENOU_TUNE_CACHE", str(tmp_path / "tune.json"))
+    sides = [100, 64, 37]
+    insts, u, m = _batch_2d(sides, 5700)
+    ref = H.Solver(2, "euler", insts, precision="mixed")
+    ur, mr = to_gpu(u), to_gpu(m, torch.float32)
+    ref.advance(ur, mr, 0.6, 1e30, 3)
+    S = H.Solver(2, "euler", insts, precision="mixed")
+    ug, mg = to_gpu(u), to_gpu(m, torch.float32)
+    w, r = S.autotune(ug, mg, reps=2)
+    assert 1 <= w <= 32 and r >= 0
+    assert (tmp_path / "tune.json").exists()
+    S.advance(ug, mg, 0.6, 1e30, 3)
+    assert torch.equal(ug, ur) and torch.equal(mg, mr)
+    # a second handle of the same class takes the cached shape
+    S2 = H.Solver(2, "euler", insts, precision="mixed")
+    assert S2.autotune(ug, mg) == (w, r)
+    for s_ in (ref, S, S2):
+        s_.close()
