@@ -80,15 +80,12 @@ __device__ __forceinline__ float rcp_nr(float x) {
 template <int NM>
 __device__ __forceinline__ void combine_factors(const SchemeParams& P, const double (&beta)[NM + 1],
                                                 double u_ave, double& a, double (&b)[NM]) {
+  // The weight mode is applied with selects rather than branches so that the
+  // whole reconstruction of a field stays one basic block.
   const double gl = P.gamma_low;
   const double g0 = 1.0 - NM * gl;
-  if (P.weights == W_LINEAR) {
-    a = 1.0;
-#pragma unroll
-    for (int m = 0; m < NM; ++m) b[m] = 0.0;
-    return;
-  }
-  if (P.weights == W_ZQ) u_ave = 1.0;
+  const bool linear = P.weights == W_LINEAR;
+  u_ave = P.weights == W_ZQ ? 1.0 : u_ave;
   double t = 0.0;
 #pragma unroll
   for (int m = 1; m <= NM; ++m) t += fabs(beta[0] - beta[m]);
@@ -104,9 +101,10 @@ __device__ __forceinline__ void combine_factors(const SchemeParams& P, const dou
   }
   const double inv = rcp_nr(sum);
   // a = w0 / g0 with w0 = wt0 / sum
-  a = (wt[0] * inv) * (NM == 2 ? P.inv_g0_1d : P.inv_g0_2d);
+  const double an = (wt[0] * inv) * (NM == 2 ? P.inv_g0_1d : P.inv_g0_2d);
+  a = linear ? 1.0 : an;
 #pragma unroll
-  for (int m = 0; m < NM; ++m) b[m] = wt[m + 1] * inv - a * gl;
+  for (int m = 0; m < NM; ++m) b[m] = linear ? 0.0 : wt[m + 1] * inv - an * gl;
 }
 
 // ---------------------------------------------------------------------------

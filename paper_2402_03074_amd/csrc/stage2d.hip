@@ -141,21 +141,32 @@ __device__ __forceinline__ void recon_scalar(const SchemeParams& P, const Sten2&
   hweno_2d<TR>(P, c, u5, u5 - S.u[3], S.u[5] - u5, u5 - S.u[1], S.u[7] - u5, asum, C);
 }
 
-// Characteristic sweep in direction DIR: combined polynomials of the four
-// fields mapped back to conserved variables, Cc[m][n].
-template <int DIR, class TR, class TM>
-__device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr,
+// One characteristic field K of the sweep in direction DIR: project the
+// stencil with row K of L, reconstruct, and return the combined polynomial C
+// together with column K of R.  The shear field (K = 2) has only two non-zero
+// entries in its L row and R column; they are used directly.
+template <int DIR, int K, class TR, class TM>
+__device__ __forceinline__ void char_field(const SchemeParams& P, const Prim& pr,
                                            const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
-                                           TR (&Cc)[4][15]) {
+                                           TR (&C)[15], double (&rcol)[4]) {
+  double lrow[4];
+  eig_row<DIR>(pr, K, lrow, rcol);
+  Sten2 W;
+  if constexpr (K == 2) {
+    // L row: -u_t at density, 1 at the tangential momentum
+    constexpr int t = DIR == 0 ? 2 : 1;
+    Sten2 S0, St;
+    read_stencil<4, TM>(B, sb, sc, st, l, 0, S0);
+    read_stencil<4, TM>(B, sb, sc, st, l, t, St);
+    const double m0 = lrow[0];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+    for (int q = 0; q < 9; ++q) W.u[q] = St.u[q] + m0 * S0.u[q];
 #pragma unroll
-    for (int n = 0; n < 15; ++n) Cc[m][n] = (TR)0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    double lrow[4], rcol[4];
-    eig_row<DIR>(pr, k, lrow, rcol);
-    Sten2 W;
+    for (int q = 0; q < 4; ++q) {
+      W.v[q] = St.v[q] + m0 * S0.v[q];
+      W.w[q] = St.w[q] + m0 * S0.w[q];
+    }
+  } else {
 #pragma unroll
     for (int q = 0; q < 9; ++q) W.u[q] = 0.0;
 #pragma unroll
@@ -173,21 +184,73 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
         W.w[q] += lm * S.w[q];
       }
     }
-    TR C[15];
-    recon_scalar<TR>(P, W, C);
+  }
+  recon_scalar<TR>(P, W, C);
+}
+
+// add R[:, K] (x) C to the conserved combined coefficients
+template <int DIR, int K, class TR>
+__device__ __forceinline__ void back_project(const TR (&C)[15], const double (&rcol)[4],
+                                             TR (&Cc)[4][15], bool first) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const TR r = (TR)rcol[m];
+  for (int m = 0; m < 4; ++m) {
+    if constexpr (K == 2) {
+      // R column of the shear field: 1 at the tangential momentum, u_t at energy
+      constexpr int t = DIR == 0 ? 2 : 1;
+      if (m != t && m != 3) continue;
+    }
+    const TR r = (TR)rcol[m];
 #pragma unroll
-      for (int n = 0; n < 15; ++n) Cc[m][n] += r * C[n];
+    for (int n = 0; n < 15; ++n) {
+      if (first)
+        Cc[m][n] = (K == 2) ? (TR)0 : r * C[n];
+      else
+        Cc[m][n] += r * C[n];
     }
   }
+}
+
+// Characteristic sweep in direction DIR: combined polynomials of the four
+// fields mapped back to conserved variables, Cc[m][n].  The entropy field
+// (K = 1) has the same left row and right column in both directions, so its
+// polynomial is reconstructed once per cell (by the first sweep) and passed
+// to the second in C1.
+template <int DIR, class TR, class TM>
+__device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr,
+                                           const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
+                                           TR (&Cc)[4][15], TR (*c1buf)[64], bool have_c1) {
+  TR C[15];
+  double rcol[4];
+  char_field<DIR, 0, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
+  back_project<DIR, 0, TR>(C, rcol, Cc, true);
+  __builtin_amdgcn_sched_barrier(0);  // keep the fields apart: bounds register pressure
+  {
+    double lrow[4], r1[4];
+    eig_row<DIR>(pr, 1, lrow, r1);
+    TR C1[15];
+    if (!have_c1) {
+      char_field<DIR, 1, TR, TM>(P, pr, B, sb, sc, st, l, C1, r1);
+#pragma unroll
+      for (int n = 0; n < 15; ++n) c1buf[n][l] = C1[n];  // parked in LDS for the other sweep
+    } else {
+#pragma unroll
+      for (int n = 0; n < 15; ++n) C1[n] = c1buf[n][l];
+    }
+    back_project<DIR, 1, TR>(C1, r1, Cc, false);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  char_field<DIR, 2, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
+  back_project<DIR, 2, TR>(C, rcol, Cc, false);
+  __builtin_amdgcn_sched_barrier(0);
+  char_field<DIR, 3, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
+  back_project<DIR, 3, TR>(C, rcol, Cc, false);
 }
 
 template <int EQ, bool CHAR, class TR, class TM>
 __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 4 : 1;
   __shared__ RowBuf<NC, TM> B;
+  __shared__ TR c1buf[15][64];  // entropy-field polynomial shared by the two sweeps
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   if (w >= A.n_waves) return;
@@ -280,7 +343,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 #pragma unroll
         for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
         pr = make_prim(gm1, U5);
-        char_sweep<1, TR, TM>(P, pr, B, sb, sc, st, lane, Cc);
+        char_sweep<1, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, false);
       } else {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
@@ -394,7 +457,8 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 
       if (row_out) {
         // ---- x-direction reconstruction of row j ----
-        if constexpr (EQ == EQ_EULER && CHAR) char_sweep<0, TR, TM>(P, pr, B, sb, sc, st, lane, Cc);
+        if constexpr (EQ == EQ_EULER && CHAR)
+          char_sweep<0, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, true);
         double F1x[NC];
         TR F2x[NC], F3x[NC];
 #pragma unroll
