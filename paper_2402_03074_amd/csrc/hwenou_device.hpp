@@ -411,6 +411,32 @@ __device__ __forceinline__ bool wave_speeds(const SchemeParams& P, const double 
   }
 }
 
+// Neighbour exchange across the 64 lanes of a wave with DPP wave shifts:
+// from_prev(x) on lane i returns x of lane i-1, from_next(x) returns x of lane
+// i+1 (lane 0 / lane 63 receive their own value; callers never use it).
+__device__ __forceinline__ float from_prev(float x) {
+  const int v = __float_as_int(x);
+  return __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_next(float x) {
+  const int v = __float_as_int(x);
+  return __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_prev(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
+}
+__device__ __forceinline__ double from_next(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
+}
+
 // wave-wide max of a non-negative double (64 lanes)
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll

@@ -107,12 +107,12 @@ __global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
     TR um[NC], up[NC], fl[NC], fr[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      um[k] = __shfl_up(pt[3][k], 1, 64);
+      um[k] = from_prev(pt[3][k]);
       up[k] = pt[0][k];
     }
     lf_flux<EQ, NC, 0, TR>(P, um, up, alpha, fl);
 #pragma unroll
-    for (int k = 0; k < NC; ++k) fr[k] = __shfl_down(fl[k], 1, 64);
+    for (int k = 0; k < NC; ++k) fr[k] = from_next(fl[k]);
 
     // volume term: Gauss-Lobatto quadrature of f over the cell
     TR vol[NC];

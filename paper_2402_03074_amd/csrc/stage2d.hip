@@ -334,6 +334,23 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
     for (int j = r0 - 1; j <= r1; ++j) {
       const bool row_out = j >= r0 && j < r1;
       const int sb = slot_of(j - 1), sc = slot_of(j), st = slot_of(j + 1);
+      const bool fin = j - 1 >= r0 && j - 1 < r1;  // row j-1 is finished in this step
+
+      // base (u^n, v^n, w^n) of row j-1: the mixed kernel has the registers to
+      // load it now and use it after the y-sweep; the FP64 kernel loads it
+      // when the row is finished
+      constexpr bool early_base = sizeof(TR) == 4;
+      double ubase[NC];
+      TM vbase[NC], wbase[NC];
+      if (early_base && A.stage != 0 && fin && col_owner) {
+        const long long o = I.offset + (long long)(j - 1) * nx + i;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          ubase[k] = A.u_base[k * plane + o];
+          vbase[k] = A.m_base[k * plane + o];
+          wbase[k] = A.m_base[(NC + k) * plane + o];
+        }
+      }
 
       // ---- reconstruction of row j, y-direction ----
       TR Cc[NC][15];
@@ -422,14 +439,19 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
       for (int k = 0; k < NC; ++k) whn[k] = qw_2d<TR>(Cc[k]);
 
       // ---- row j-1 is complete: Runge-Kutta update and store ----
-      if (j - 1 >= r0 && j - 1 < r1) {
+      if (fin) {
         if (col_owner) {
           const long long o = I.offset + (long long)(j - 1) * nx + i;
           double Uo[NC];
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             const double uin = B.u[sb][k][lane + 1];
-            const double ub = A.stage == 0 ? 0.0 : A.u_base[k * plane + o];
+            if (!early_base && A.stage != 0) {
+              ubase[k] = A.u_base[k * plane + o];
+              vbase[k] = A.m_base[k * plane + o];
+              wbase[k] = A.m_base[(NC + k) * plane + o];
+            }
+            const double ub = A.stage == 0 ? 0.0 : ubase[k];
             const double un = ra * ub + rb * (uin + dt * F1p[k]);
             TR vn, wn;
             if (A.stage == 0) {
@@ -438,8 +460,8 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
               vn = vhp[k] + (TR)dt * F2p[k];
               wn = whp[k] + (TR)dt * F3p[k];
             } else {
-              const TR vb = (TR)A.m_base[k * plane + o];
-              const TR wb = (TR)A.m_base[(NC + k) * plane + o];
+              const TR vb = (TR)vbase[k];
+              const TR wb = (TR)wbase[k];
               vn = (TR)ra * vb + (TR)rb * (vhp[k] + (TR)dt * F2p[k]);
               wn = (TR)ra * wb + (TR)rb * (whp[k] + (TR)dt * F3p[k]);
             }
@@ -489,10 +511,10 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
           // x_{i-1/2} at eta_H: u- = left lane at +1/2, u+ = this lane at -1/2
           TR um[NC], fl[NC], fr[NC];
 #pragma unroll
-          for (int k = 0; k < NC; ++k) um[k] = __shfl_up(xp[k], 1, 64);
+          for (int k = 0; k < NC; ++k) um[k] = from_prev(xp[k]);
           lf_flux<EQ, NC, 0, TR>(P, um, xm, a1, fl);
 #pragma unroll
-          for (int k = 0; k < NC; ++k) fr[k] = __shfl_down(fl[k], 1, 64);
+          for (int k = 0; k < NC; ++k) fr[k] = from_next(fl[k]);
           const TR wg = (TR)g3w(H);
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
