@@ -33,22 +33,58 @@ __global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
     const InstDev I = A.inst[wk.inst];
     const int n = I.nx;
     int i = wk.a - 1 + lane;
-    if (i > n) i = n;  // lanes past the right neighbour: harmless duplicates
+    // lanes past the right ring lane (i = n) take i = n + 1: the ring lane reads
+    // its right neighbour from the next lane; lanes further right are unused
+    if (i > n + 1) i = n + 1;
     const bool owner = lane >= 1 && lane <= kStripWidth && i < n;
     const int im = wrap_index(i - 1, n, I.bc[0], I.bc[1]);
     const int ic = wrap_index(i, n, I.bc[0], I.bc[1]);
     const int ip = wrap_index(i + 1, n, I.bc[0], I.bc[1]);
     const double* u = A.u_in + I.offset;
     const TM* m = A.m_in + I.offset;
+    const long long o = I.offset + i;
 
-    double Um[NC], Uc[NC], Up[NC], Vm[NC], Vp[NC];
+    // Every lane loads its own cell; the neighbours' values come from the
+    // adjacent lanes, except at the two ends of the wave, which load them.
+    // The Runge-Kutta base of the owned cell is loaded up front as well.
+    double Um[NC], Uc[NC], Up[NC], Vm[NC], Vp[NC], Ub[NC];
+    TM Mb[NC];
+    TM Vc[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      Um[k] = u[k * plane + im];
       Uc[k] = u[k * plane + ic];
-      Up[k] = u[k * plane + ip];
-      Vm[k] = (double)m[k * plane + im];
-      Vp[k] = (double)m[k * plane + ip];
+      Vc[k] = m[k * plane + ic];
+      if (A.stage != 0 && owner) {
+        Ub[k] = A.u_base[k * plane + o];
+        Mb[k] = A.m_base[k * plane + o];
+      }
+    }
+    const bool edge_lo = lane == 0, edge_hi = lane == 63;
+    double Uend[NC];
+    TM Vend[NC];
+    if (edge_lo || edge_hi) {
+      const int ie = edge_lo ? im : ip;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        Uend[k] = u[k * plane + ie];
+        Vend[k] = m[k * plane + ie];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      Um[k] = from_prev(Uc[k]);
+      Up[k] = from_next(Uc[k]);
+      const TM vm = from_prev(Vc[k]), vp = from_next(Vc[k]);
+      Vm[k] = (double)vm;
+      Vp[k] = (double)vp;
+      if (edge_lo) {
+        Um[k] = Uend[k];
+        Vm[k] = (double)Vend[k];
+      }
+      if (edge_hi) {
+        Up[k] = Uend[k];
+        Vp[k] = (double)Vend[k];
+      }
     }
 
     // ---- reconstruction: point values at the 4 Gauss-Lobatto nodes, v^ ----
@@ -137,19 +173,18 @@ __global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
     const double idx = 1.0 / I.dx;
     double Uo[NC];
     if (owner) {
-      const long long o = I.offset + i;
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
         const double F1 = -((double)fr[k] - (double)fl[k]) * idx;
         const TR F2 = -(fl[k] + fr[k]) * (TR)(0.5 * idx) + vol[k] * (TR)idx;
-        const double ub = A.stage == 0 ? 0.0 : A.u_base[k * plane + o];
+        const double ub = A.stage == 0 ? 0.0 : Ub[k];
         const double un = ra * ub + rb * (Uc[k] + dt * F1);
         TR mn;
         if (A.stage == 0) {
           A.m_base[k * plane + o] = (TM)vh[k];
           mn = vh[k] + (TR)dt * F2;
         } else {
-          const TR mb = (TR)A.m_base[k * plane + o];
+          const TR mb = (TR)Mb[k];
           mn = (TR)ra * mb + (TR)rb * (vh[k] + (TR)dt * F2);
         }
         A.u_out[k * plane + o] = un;
