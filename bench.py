@@ -1,17 +1,24 @@
 """Benchmark of the HWENO-U hot path on one MI355X.
 
-Workload: 2D Euler (gamma = 1.4) on a 2048 x 2048 periodic grid of [0, 10]^2,
-seeded four-quadrant Riemann data (rho in [0.1, 1.5], p in [0.03, 1.5],
-u, v in [-0.5, 0.5]) times an isentropic vortex of strength 5, CFL 0.6,
-modified SSP-RK3.  One benchmark step = one full Runge-Kutta step: the max
-wave speed / dt, and three fused stages (reconstruction, weights, moment
-modification, fluxes, update), replayed from a captured HIP graph.
+Default workload: 2D Euler (gamma = 1.4) on a 2048 x 2048 periodic grid of
+[0, 10]^2, seeded four-quadrant Riemann data (rho in [0.1, 1.5], p in
+[0.03, 1.5], u, v in [-0.5, 0.5]) times an isentropic vortex of strength 5,
+CFL 0.6, modified SSP-RK3.  One benchmark step = one full Runge-Kutta step:
+the max wave speed / dt, and three fused stages (reconstruction, weights,
+moment modification, fluxes, update), replayed from a captured HIP graph.
 
-Reported: cell-stage updates per second of the mixed form (`value`) and of the
-plain FP64 form, the mixed-vs-FP64 L1 difference after the timed run, the
-stage kernel's roofline position, and the CPU oracle on a bounded sample.
+Reported on the default workload: cell-stage updates per second of the mixed
+form (`value`) and of the plain FP64 form, the same for component-wise
+reconstruction, the mixed-vs-FP64 L1 difference after the timed run next to
+the FP64 difference between the 1024^2 and 2048^2 solutions at the same time,
+the stage kernel's roofline position, and the CPU oracle on a bounded sample.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N] [--no-cpu-baseline]
+--workload names one of the other workloads (1D advection N = 200, 1D Euler
+N = 65536, 512 x 1D Euler, 64 x 2D Euler); it prints one line of the same
+form for it.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                  [--size N] [--no-cpu-baseline] [--no-extras]
 """
 import argparse
 import json
@@ -34,6 +41,22 @@ KERNEL_SOURCES = ["paper_2402_03074_amd/csrc/stage2d.hip",
                   "paper_2402_03074_amd/csrc/hwenou_device.hpp",
                   "paper_2402_03074_amd/csrc/hwenou_internal.hpp"]
 COUNTERS_FILE = "profiles/stage2d_euler_2048_counters.md"
+DEFAULT_WORKLOAD = "euler2d-2048"
+WORKLOADS = {
+    "euler2d-2048": "2D Euler {n}x{n} periodic on [0,10]^2, seeded four-quadrant Riemann data "
+                    "x isentropic vortex (strength 5), CFL 0.6, modified SSP-RK3, "
+                    "characteristic-wise HWENO-U",
+    "advection1d-200": "1D linear advection u_t + u_x = 0, N = 200 periodic on [0,2], "
+                       "u0 = sin(pi x), CFL 0.2 (1000 steps reach T = 2)",
+    "euler1d-65536": "1D Euler N = 65536 transmissive on [0,1], seeded 16-interface "
+                     "shock tube with a density wave, CFL 0.6, characteristic-wise",
+    "euler1d-batch512": "512 independent 1D Euler shock tubes, N log-uniform in "
+                        "[256, 65536], one persistent launch per stage, per-instance dt",
+    "euler2d-batch64": "64 independent 2D Euler vortex+quadrant grids, sides log-uniform "
+                       "in [256, 1024], one persistent launch per stage, per-instance dt",
+}
+DEFAULT_STEPS = {"euler2d-2048": 50, "advection1d-200": 1000, "euler1d-65536": 200,
+                 "euler1d-batch512": 200, "euler2d-batch64": 50}
 
 
 def kernel_source_hash():
@@ -53,8 +76,6 @@ def recorded_counters():
     try:
         with open(os.path.join(ROOT, COUNTERS_FILE)) as fh:
             for line in fh:
-                if line.startswith("| ") and ":" not in line and "|" in line[2:]:
-                    continue
                 if line.startswith("- ") and ":" in line:
                     k, v = line[2:].split(":", 1)
                     out[k.strip()] = v.strip().strip("`")
@@ -62,65 +83,117 @@ def recorded_counters():
         pass
     return out
 
-# algorithmic HBM bytes per cell and stage (state read, base read, write;
-# stage 0 also writes the modified moments); 2D Euler: 4 components
-def stage_bytes(precision, stage):
+
+def stage_bytes(dim, ncomp, precision, stage):
+    """Algorithmic HBM bytes per cell of one stage: the state read, the
+    Runge-Kutta base read (stages 1, 2), the output written, and in stage 0
+    the modified moments written.  Halo re-reads are not counted."""
     mb = 8 if precision == "fp64" else 4
-    state = 4 * 8 + 2 * 4 * mb  # averages FP64 + two moment directions
-    moments = 2 * 4 * mb
+    moments = dim * ncomp * mb
+    state = ncomp * 8 + moments
     if stage == 0:
         return state + state + moments
-    return state + (4 * 8 + moments) + state
+    return state + (ncomp * 8 + moments) + state
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--size", type=int, default=2048)
+    p.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    p.add_argument("--size", type=int, default=2048, help="grid side of euler2d-2048")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--precisions", default="mixed,fp64")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the component-wise and mesh-difference runs")
+    p.add_argument("--precisions", default=None)
     p.add_argument("--tune", action="store_true",
                    help="run the launch-shape autotuner first (default: the library's "
-                        "occupancy-based launch shape)")
+                        "occupancy-based launch shape; the batched workloads always tune)")
     return p.parse_args()
 
 
-def run_precision(H, torch, u0, m0, n, precision, steps, warmup, tune):
-    inst = H.make_inst(n, n, (0.0, 10.0, 0.0, 10.0), "periodic")
-    S = H.Solver(2, "euler", [inst], precision=precision)
-    ug = torch.tensor(u0.reshape(4, -1), device="cuda")
-    mg = torch.tensor(m0.reshape(2, 4, -1), device="cuda").to(S.mom_dtype)
+class Case:
+    """Problem set-up of one workload: instances, initial state, CFL."""
+
+    def __init__(self, name, dim, eq, insts, u0, m0, cfl=0.6, kw=None, label=""):
+        self.name, self.dim, self.eq, self.insts = name, dim, eq, insts
+        self.u0, self.m0, self.cfl, self.kw, self.label = u0, m0, cfl, kw or {}, label
+        self.ncomp = u0.shape[0]
+        self.cells = u0.shape[1]
+
+
+def make_case(H, W, np, name, n=2048):
+    label = WORKLOADS[name].format(n=n)
+    if name == "euler2d-2048":
+        u0, m0 = W.euler_2d_vortex_quadrant(n, seed=3000, q=3)
+        return Case(name, 2, "euler", [H.make_inst(n, n, (0.0, 10.0, 0.0, 10.0), "periodic")],
+                    u0.reshape(4, -1), m0.reshape(2, 4, -1), label=label)
+    if name == "advection1d-200":
+        u0, m0 = W.advection_sine_1d(200)
+        return Case(name, 1, "advection", [H.make_inst(200, 1, (0.0, 2.0))], u0, m0, cfl=0.2,
+                    kw={"adv": (1.0, 0.0)}, label=label)
+    if name == "euler1d-65536":
+        u0, m0 = W.euler_1d_shocktube(65536, seed=2000)
+        return Case(name, 1, "euler", [H.make_inst(65536, 1, (0.0, 1.0), "transmissive")],
+                    u0, m0, label=label)
+    if name == "euler1d-batch512":
+        sizes, data = W.batch_1d_euler()
+        insts, off = [], 0
+        for s in sizes:
+            insts.append(H.make_inst(int(s), 1, (0.0, 1.0), "transmissive", offset=off))
+            off += int(s)
+        u0 = np.concatenate([d[0] for d in data], axis=1)
+        m0 = np.concatenate([d[1] for d in data], axis=2)
+        return Case(name, 1, "euler", insts, u0, m0, label=label)
+    if name == "euler2d-batch64":
+        sides, data = W.batch_2d_euler()
+        insts, off = [], 0
+        for s in sides:
+            insts.append(H.make_inst(int(s), int(s), (0.0, 10.0, 0.0, 10.0), "periodic",
+                                     offset=off))
+            off += int(s) ** 2
+        u0 = np.concatenate([d[0].reshape(4, -1) for d in data], axis=1)
+        m0 = np.concatenate([d[1].reshape(2, 4, -1) for d in data], axis=2)
+        return Case(name, 2, "euler", insts, u0, m0, label=label)
+    raise ValueError(name)
+
+
+def run_case(H, torch, case, precision, steps, warmup, tune, char_decomp=True):
+    S = H.Solver(case.dim, case.eq, case.insts, precision=precision, char_decomp=char_decomp,
+                 **case.kw)
+    ug = torch.tensor(case.u0, device="cuda")
+    mg = torch.tensor(case.m0, device="cuda").to(S.mom_dtype)
     launch = S.autotune(ug, mg) if tune else None
     # warm-up steps (untimed), then exactly `steps` timed steps
     if warmup > 0:
-        S.advance(ug, mg, 0.6, 1e30, warmup)
+        S.advance(ug, mg, case.cfl, 1e30, warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record()
-    tg, sg = S.advance(ug, mg, 0.6, 1e30, steps)
+    tg, sg = S.advance(ug, mg, case.cfl, 1e30, steps)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
-    assert sg == [steps], sg
+    assert sg == [steps] * len(case.insts), sg
 
     # The timed region is graph replays of whole steps: per step one dt and
     # one finish kernel (single blocks, ~9 us together by the kernel trace)
     # and three launches of the stage kernel, so the stage kernel's average
     # launch duration over the timed region is (region / steps - aux) / 3.
-    stage_ms = [(ev_ms / steps - AUX_US_PER_STEP * 1e-3) / 3.0] * 3
+    stage_ms = (ev_ms / steps - AUX_US_PER_STEP * 1e-3) / 3.0
     status = H.hwenou_status(S.h)
     out = ug.cpu().numpy(), mg.double().cpu().numpy()
     S.close()
     del ug, mg
     torch.cuda.empty_cache()
     return {"wall_s": wall, "event_ms": ev_ms, "stage_ms": stage_ms, "state": out,
-            "t": tg[0], "status": status, "launch": launch}
+            "t": tg, "status": status, "launch": launch,
+            "rate": case.cells * 3 * steps / (ev_ms * 1e-3), "ms_per_step": ev_ms / steps}
 
 
 def copy_calibration(torch, mib=1024):
@@ -137,10 +210,12 @@ def copy_calibration(torch, mib=1024):
     return mib
 
 
-def cpu_baseline(u0, m0, n):
+def cpu_baseline(W, u0, m0, n):
     """The oracle (plain C, FP64, OpenMP) on a bounded sample of the same
-    workload: one Runge-Kutta step (three stages) over the full grid."""
-    from oracle.driver import Problem, num_threads
+    workload: one Runge-Kutta step (three stages) over the full grid on all
+    host threads, and one step of the same data generated on a 256^2 grid on
+    one thread."""
+    from oracle.driver import Problem, num_threads, set_num_threads
     P = Problem(2, "euler", (n, n), (0.0, 10.0, 0.0, 10.0))
     alpha = P.max_wavespeed(u0)
     dt = P.dt_from(alpha, 0.6)
@@ -148,10 +223,64 @@ def cpu_baseline(u0, m0, n):
     P.step(u0, m0, dt, alpha)
     el = time.perf_counter() - t0
     cs = 3 * n * n
-    return {"value": cs / el, "unit": "cell-stage/s", "cores": num_threads(),
-            "kind": "oracle",
-            "sample": f"one Runge-Kutta step (3 stages) of the same {n}x{n} 2D Euler data, "
-                      f"{cs} cell-stages in {el:.2f} s"}
+    threads = num_threads()
+    out = {"value": cs / el, "unit": "cell-stage/s", "cores": threads, "kind": "oracle",
+           "sample": f"one Runge-Kutta step (3 stages) of the same {n}x{n} 2D Euler data, "
+                     f"{cs} cell-stages in {el:.2f} s"}
+    m = 256
+    us, ms = W.euler_2d_vortex_quadrant(m, seed=3000, q=3)
+    P1 = Problem(2, "euler", (m, m), (0.0, 10.0, 0.0, 10.0))
+    a1 = P1.max_wavespeed(us)
+    set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        P1.step(us, ms, P1.dt_from(a1, 0.6), a1)
+        el1 = time.perf_counter() - t0
+    finally:
+        set_num_threads(threads)
+    out["one_thread"] = {"value": 3 * m * m / el1, "unit": "cell-stage/s", "cores": 1,
+                         "sample": f"one Runge-Kutta step of the same data on a {m}x{m} grid, "
+                                   f"{3 * m * m} cell-stages in {el1:.2f} s"}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            out["cpu_model"] = next(l.split(":", 1)[1].strip() for l in fh
+                                    if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return out
+
+
+def mesh_difference(H, W, torch, np, n, t_final):
+    """FP64 density L1 difference between the 2048^2 solution and the
+    1024^2 solution of the same data at the same time: the size of the
+    discretisation error against which the mixed-vs-FP64 difference is set."""
+    c = n // 2
+    u0, m0 = W.euler_2d_vortex_quadrant(c, seed=3000, q=3)
+    S = H.Solver(2, "euler", [H.make_inst(c, c, (0.0, 10.0, 0.0, 10.0), "periodic")])
+    ug = torch.tensor(u0.reshape(4, -1), device="cuda")
+    mg = torch.tensor(m0.reshape(2, 4, -1), device="cuda")
+    t, s = S.advance(ug, mg, 0.6, t_final, 10 ** 6)
+    coarse = ug.cpu().numpy()[0].reshape(c, c)
+    S.close()
+    return coarse, t[0], s[0]
+
+
+def summary_roofline(case, r, precision, rec):
+    cells = case.cells
+    kavg = r["stage_ms"]
+    byts = sum(stage_bytes(case.dim, case.ncomp, precision, s) for s in range(3)) / 3
+    hbm = byts * cells / (kavg * 1e-3) / 1e9
+    if case.dim == 2 and case.eq == "euler":
+        flops = float(rec.get(f"algorithmic_flops_per_cell_stage_{precision}", "nan"))
+        tf = flops * cells / (kavg * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": tf, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / VALU_PEAK_TFLOPS, "kernel": "stage2d_kernel",
+                "avg_launch_ms": kavg, "flops_per_cell_stage": flops}, \
+            {"achieved_algorithmic": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": hbm / HBM_PEAK_GBS, "bytes_per_cell_stage": byts}
+    return {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": hbm / HBM_PEAK_GBS, "traffic": None, "kernel": "stage1d_kernel",
+            "avg_launch_ms": kavg, "bytes_per_cell_stage": byts}, None
 
 
 def main():
@@ -166,87 +295,93 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    name = args.workload
     n = args.size
-    print(f"[bench] generating {n}x{n} vortex + quadrant data", file=sys.stderr, flush=True)
-    u0, m0 = W.euler_2d_vortex_quadrant(n, seed=3000, q=3)
-    cells = n * n
+    steps = args.steps if args.steps is not None else DEFAULT_STEPS[name]
+    precs = (args.precisions or ("fp64" if name == "advection1d-200" else "mixed,fp64"))
+    precs = precs.split(",")
+    print(f"[bench] generating {name}", file=sys.stderr, flush=True)
+    case = make_case(H, W, np, name, n)
+    tune = args.tune or name.endswith(("batch512", "batch64"))
     results = {}
-    for prec in args.precisions.split(","):
-        print(f"[bench] {prec}: {args.warmup} warm-up + {args.steps} timed steps",
+    for prec in precs:
+        print(f"[bench] {prec}: {args.warmup} warm-up + {steps} timed steps",
               file=sys.stderr, flush=True)
-        results[prec] = run_precision(H, torch, u0, m0, n, prec, args.steps, args.warmup,
-                                      args.tune)
-        r = results[prec]
-        print(f"[bench] {prec}: {r['event_ms'] / args.steps:.3f} ms/step, stages "
-              f"{[round(x, 3) for x in r['stage_ms']]} ms", file=sys.stderr, flush=True)
+        results[prec] = r = run_case(H, torch, case, prec, steps, args.warmup, tune)
+        print(f"[bench] {prec}: {r['ms_per_step']:.3f} ms/step, stage {r['stage_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
 
-    def summary(prec):
-        r = results[prec]
-        ms_step = r["event_ms"] / args.steps
-        rate = cells * 3 * args.steps / (r["event_ms"] * 1e-3)
-        byts = [stage_bytes(prec, s) * cells for s in range(3)]
-        kms = sum(r["stage_ms"])
-        achieved = sum(byts) / (kms * 1e-3) / 1e9
-        return ms_step, rate, achieved, kms / 3
-
-    head = "mixed" if "mixed" in results else list(results)[0]
-    ms_step, rate, achieved, kavg = summary(head)
     rec = recorded_counters()
     fresh = rec.get("source_sha256") == kernel_source_hash()
-    flops_cs = float(rec.get(f"algorithmic_flops_per_cell_stage_{head}", "nan"))
-    alu_tflops = flops_cs * cells / (kavg * 1e-3) / 1e12
-    traffic = None
-    if fresh and f"hbm_bytes_per_launch_{head}" in rec:
-        traffic = float(rec[f"hbm_bytes_per_launch_{head}"])
+    head = precs[0]
+    r = results[head]
+    roof, hbm = summary_roofline(case, r, head, rec)
+    if roof["bound"] == "alu":
+        roof["counters_current"] = fresh
+        roof["traffic"] = (float(rec[f"hbm_bytes_per_launch_{head}"])
+                           if fresh and case.name == DEFAULT_WORKLOAD
+                           and f"hbm_bytes_per_launch_{head}" in rec else None)
     line = {
-        "metric": METRIC,
-        "value": rate,
+        "metric": METRIC if name == DEFAULT_WORKLOAD else "cell-stage updates/s",
+        "value": r["rate"],
         "unit": "cell-stage/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32" if head == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"2D Euler {n}x{n} periodic on [0,10]^2, seeded four-quadrant "
-                               "Riemann data x isentropic vortex (strength 5), CFL 0.6, "
-                               "modified SSP-RK3, characteristic-wise HWENO-U",
-                   "precision": head, "cells": cells, "seed": 3000},
-        "roofline": {"bound": "alu", "achieved": alu_tflops, "peak": VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": alu_tflops / VALU_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "stage2d_kernel", "avg_launch_ms": kavg,
-                     "flops_per_cell_stage": flops_cs, "counters_current": fresh},
-        "hbm": {"achieved_algorithmic": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS,
-                "bytes_per_cell_stage": sum(stage_bytes(head, s) for s in range(3)) / 3},
+        "config": {"workload": case.label, "precision": head, "cells": case.cells,
+                   "instances": len(case.insts)},
+        "roofline": roof,
     }
-    for prec in results:
-        if prec == head:
-            continue
-        ms2, rate2, ach2, kavg2 = summary(prec)
-        fl2 = float(rec.get(f"algorithmic_flops_per_cell_stage_{prec}", "nan"))
-        tf2 = fl2 * cells / (kavg2 * 1e-3) / 1e12
-        line[prec] = {"value": rate2, "ms_per_step": ms2, "hbm_achieved_gbs": ach2,
-                      "hbm_frac": ach2 / HBM_PEAK_GBS, "avg_stage_launch_ms": kavg2,
-                      "alu_tflops": tf2, "alu_frac": tf2 / VALU_PEAK_TFLOPS}
-        line["mixed_speedup_vs_fp64"] = rate / rate2 if head == "mixed" else None
+    if hbm is not None:
+        line["hbm"] = hbm
+    for prec in precs[1:]:
+        r2 = results[prec]
+        roof2, hbm2 = summary_roofline(case, r2, prec, rec)
+        line[prec] = {"value": r2["rate"], "ms_per_step": r2["ms_per_step"],
+                      "avg_stage_launch_ms": r2["stage_ms"], "roofline": roof2}
+        if hbm2 is not None:
+            line[prec]["hbm"] = hbm2
+        line[f"{head}_speedup_vs_{prec}"] = r["rate"] / r2["rate"]
     if "mixed" in results and "fp64" in results:
         a = results["mixed"]["state"][0]
         b = results["fp64"]["state"][0]
         line["mixed_vs_fp64"] = {
             "l1_rho_diff": float(np.abs(a[0] - b[0]).mean()),
             "rel_linf_rho_diff": float(np.abs(a[0] - b[0]).max() / np.abs(b[0]).max()),
-            "after_steps": args.warmup + args.steps}
+            "after_steps": args.warmup + steps}
+    if name == DEFAULT_WORKLOAD and not args.no_extras:
+        cw = {}
+        for prec in precs:
+            print(f"[bench] component-wise {prec}", file=sys.stderr, flush=True)
+            rc = run_case(H, torch, case, prec, steps, args.warmup, False, char_decomp=False)
+            cw[prec] = {"value": rc["rate"], "ms_per_step": rc["ms_per_step"],
+                        "status": rc["status"]}
+        line["componentwise"] = cw
+        if "fp64" in results and n % 2 == 0 and "mixed_vs_fp64" in line:
+            print("[bench] FP64 mesh difference", file=sys.stderr, flush=True)
+            tf = results["fp64"]["t"][0]
+            coarse, tc, sc = mesh_difference(H, W, torch, np, n, tf)
+            fine = results["fp64"]["state"][0][0].reshape(n, n)
+            fine_c = fine.reshape(n // 2, 2, n // 2, 2).mean(axis=(1, 3))
+            md = float(np.abs(fine_c - coarse).mean())
+            line["mixed_vs_fp64"].update({
+                "t": tf, "fp64_l1_rho_mesh_diff": md, "mesh_diff_coarse_steps": sc,
+                "mesh_diff_t_match": abs(tc - tf),
+                "mixed_diff_over_mesh_diff": line["mixed_vs_fp64"]["l1_rho_diff"] / md})
     line["status"] = {p: results[p]["status"] for p in results}
     line["launch"] = {p: results[p]["launch"] for p in results}
     line["kernel_source_sha256"] = kernel_source_hash()
     line["copy_calibration_mib"] = copy_calibration(torch)
-    if not args.no_cpu_baseline:
+    if name == DEFAULT_WORKLOAD and not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(u0, m0, n)
+        line["cpu_baseline"] = cpu_baseline(W, case.u0.reshape(4, n, n),
+                                            case.m0.reshape(2, 4, n, n), n)
     print(json.dumps(line))
 
 

@@ -67,6 +67,7 @@ def lib():
     L.oracle_max_wavespeed.argtypes = [C.POINTER(_Params), C.c_int, C.c_size_t, dp, dp]
     L.oracle_all_physical.argtypes = [C.POINTER(_Params), C.c_int, C.c_size_t, dp]
     L.oracle_num_threads.restype = C.c_int
+    L.oracle_set_num_threads.argtypes = [C.c_int]
     # hand in the exactly derived operators
     r1 = derive.recon_1d()
     keep = [_flat(r1["M0"]), _flat(r1["M1"]), _flat(r1["M2"]), _flat(derive.beta_gram_1d(4)),
@@ -89,6 +90,12 @@ def lib():
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n):
+    """Thread count of later oracle calls (timing only; results do not depend
+    on it: every cell is computed independently)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def _ptr(a):

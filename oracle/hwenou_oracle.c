@@ -709,3 +709,13 @@ int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Thread count of later calls (timing only; results do not depend on it). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
