@@ -92,7 +92,9 @@ typedef struct hwenou_handle hwenou_handle;
  * hwenou_advance, the stored modified moments of stage 0, per-instance
  * alpha/dt/t/step arrays and the work lists.  Errors: EINVAL (dim, eq,
  * precision or weights out of range; n_inst < 1; nx or ny < 3; overlapping
- * instances; gas_gamma <= 1 for Euler), ENOMEM, EHIP.  On error *out is NULL. */
+ * instances; gas_gamma <= 1 for Euler), EUNSUPPORTED (an instance of more than
+ * 2^29 cells: the kernels address an instance with 32-bit byte offsets),
+ * ENOMEM, EHIP.  On error *out is NULL. */
 int hwenou_create(const hwenou_desc* desc, int n_inst, const hwenou_inst* inst, void* stream,
                   hwenou_handle** out);
 

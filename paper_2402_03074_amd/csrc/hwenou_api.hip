@@ -309,7 +309,7 @@ int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, voi
         return HWENOU_EINVAL;
     if (I.offset < 0) return HWENOU_EINVAL;
     const long long n = (long long)I.nx * ny;
-    if (n > (1LL << 31)) return HWENOU_EUNSUPPORTED;
+    if (n > (1LL << 29)) return HWENOU_EUNSUPPORTED;  // 32-bit byte offsets in the kernels
     ranges.push_back({I.offset, I.offset + n});
     plane = std::max(plane, (long long)(I.offset + n));
   }

@@ -53,6 +53,19 @@ __device__ __forceinline__ int wrap_index(int i, int n, int bc_lo, int bc_hi) {
   return i;
 }
 
+// Global memory access through a wave-uniform base pointer (row and
+// component folded in with scalar arithmetic) and a 32-bit per-lane byte
+// offset, which halves the registers that hold per-lane offsets.  Offsets
+// stay below 2^32 bytes because an instance holds at most 2^29 cells.
+template <class T>
+__device__ __forceinline__ T load_at(const T* base, unsigned byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void store_at(T* base, unsigned byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 // ---------------------------------------------------------------------------
 // reciprocals: hardware estimate refined by Newton-Raphson steps
 // r <- r + r (1 - x r); two steps in FP64, one in FP32.  Within a few ulp of

@@ -29,10 +29,10 @@
 
 namespace hwenou {
 
-constexpr int kCols = 66;
+constexpr int kCols = 66;  // LDS columns: strip*62 - 2 .. strip*62 + 63
 #ifndef HWENOU_2D_WAVES
 #define HWENOU_2D_WAVES 1
-#endif  // LDS columns: strip*62 - 2 .. strip*62 + 63
+#endif
 
 __device__ __forceinline__ double g3w(int g) { return g == 1 ? G3W1 : G3W0; }
 __device__ __forceinline__ double g3x(int g) { return g == 0 ? -G3S : (g == 1 ? 0.0 : G3S); }
@@ -270,6 +270,10 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
     int i = c0 - 1 + lane;
     if (i > nx) i = nx;
     const bool col_owner = lane >= 1 && lane <= kStripWidth && i < nx;
+    // byte offsets of this lane's column in a row (clamped into the row, so
+    // that loads need no lane mask; only owners store)
+    const int ic = min(max(i, 0), nx - 1);
+    const unsigned ou = (unsigned)ic * 8u, om = (unsigned)ic * (unsigned)sizeof(TM);
     const TR a1 = (TR)A.alpha[2 * wk.inst], a2 = (TR)A.alpha[2 * wk.inst + 1];
     const double dt = A.dt[wk.inst];
     const double idx = 1.0 / I.dx, idy = 1.0 / I.dy;
@@ -281,6 +285,8 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
     const int gx0 = wrap_index(min(c0 - 2 + lane, nx + 1), nx, I.bc[0], I.bc[1]);
     const int gx1 = wrap_index(min(c0 + 62 + lane, nx + 1), nx, I.bc[0], I.bc[1]);
     const bool extra = lane < 2;
+    const unsigned o0u = (unsigned)gx0 * 8u, o0m = (unsigned)gx0 * (unsigned)sizeof(TM);
+    const unsigned o1u = (unsigned)gx1 * 8u, o1m = (unsigned)gx1 * (unsigned)sizeof(TM);
 
     // register prefetch of one row (this lane's column and, for lanes 0-1,
     // one of the two extra columns)
@@ -290,13 +296,16 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
       const long long base = (long long)wrap_index(row, ny, I.bc[2], I.bc[3]) * nx;
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
-        pu0[k] = u_in[k * plane + base + gx0];
-        pm0[0][k] = m_in[k * plane + base + gx0];
-        pm0[1][k] = m_in[(NC + k) * plane + base + gx0];
+        const double* pu = u_in + (k * plane + base);
+        const TM* pv = m_in + (k * plane + base);
+        const TM* pw = m_in + ((NC + k) * plane + base);
+        pu0[k] = load_at(pu, o0u);
+        pm0[0][k] = load_at(pv, o0m);
+        pm0[1][k] = load_at(pw, o0m);
         if (extra) {
-          pu1[k] = u_in[k * plane + base + gx1];
-          pm1[0][k] = m_in[k * plane + base + gx1];
-          pm1[1][k] = m_in[(NC + k) * plane + base + gx1];
+          pu1[k] = load_at(pu, o1u);
+          pm1[0][k] = load_at(pv, o1m);
+          pm1[1][k] = load_at(pw, o1m);
         }
       }
     };
@@ -342,13 +351,13 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
       constexpr bool early_base = sizeof(TR) == 4;
       double ubase[NC];
       TM vbase[NC], wbase[NC];
-      if (early_base && A.stage != 0 && fin && col_owner) {
-        const long long o = I.offset + (long long)(j - 1) * nx + i;
+      const long long orow = I.offset + (long long)(j - 1) * nx;  // row j-1
+      if (early_base && A.stage != 0 && fin) {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-          ubase[k] = A.u_base[k * plane + o];
-          vbase[k] = A.m_base[k * plane + o];
-          wbase[k] = A.m_base[(NC + k) * plane + o];
+          ubase[k] = load_at(A.u_base + (k * plane + orow), ou);
+          vbase[k] = load_at(A.m_base + (k * plane + orow), om);
+          wbase[k] = load_at(A.m_base + ((NC + k) * plane + orow), om);
         }
       }
 
@@ -440,23 +449,25 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 
       // ---- row j-1 is complete: Runge-Kutta update and store ----
       if (fin) {
+        if (!early_base && A.stage != 0) {
+#pragma unroll
+          for (int k = 0; k < NC; ++k) {
+            ubase[k] = load_at(A.u_base + (k * plane + orow), ou);
+            vbase[k] = load_at(A.m_base + (k * plane + orow), om);
+            wbase[k] = load_at(A.m_base + ((NC + k) * plane + orow), om);
+          }
+        }
         if (col_owner) {
-          const long long o = I.offset + (long long)(j - 1) * nx + i;
           double Uo[NC];
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             const double uin = B.u[sb][k][lane + 1];
-            if (!early_base && A.stage != 0) {
-              ubase[k] = A.u_base[k * plane + o];
-              vbase[k] = A.m_base[k * plane + o];
-              wbase[k] = A.m_base[(NC + k) * plane + o];
-            }
             const double ub = A.stage == 0 ? 0.0 : ubase[k];
             const double un = ra * ub + rb * (uin + dt * F1p[k]);
             TR vn, wn;
             if (A.stage == 0) {
-              A.m_base[k * plane + o] = (TM)vhp[k];
-              A.m_base[(NC + k) * plane + o] = (TM)whp[k];
+              store_at(A.m_base + (k * plane + orow), om, (TM)vhp[k]);
+              store_at(A.m_base + ((NC + k) * plane + orow), om, (TM)whp[k]);
               vn = vhp[k] + (TR)dt * F2p[k];
               wn = whp[k] + (TR)dt * F3p[k];
             } else {
@@ -465,9 +476,9 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
               vn = (TR)ra * vb + (TR)rb * (vhp[k] + (TR)dt * F2p[k]);
               wn = (TR)ra * wb + (TR)rb * (whp[k] + (TR)dt * F3p[k]);
             }
-            A.u_out[k * plane + o] = un;
-            A.m_out[k * plane + o] = (TM)vn;
-            A.m_out[(NC + k) * plane + o] = (TM)wn;
+            store_at(A.u_out + (k * plane + orow), ou, un);
+            store_at(A.m_out + (k * plane + orow), om, (TM)vn);
+            store_at(A.m_out + ((NC + k) * plane + orow), om, (TM)wn);
             Uo[k] = un;
           }
           double sx, sy;

@@ -67,6 +67,15 @@ def test_create_rejects_bad_instances():
         H.HWENOU_EINVAL
 
 
+def test_create_rejects_oversized_instance():
+    """An instance of more than 2^29 cells is refused before any device call:
+    the kernels address an instance with 32-bit byte offsets."""
+    d = H.make_desc(2, "euler")
+    assert _create(d, [H.make_inst(23171, 23171, (0, 1, 0, 1))])[0] == H.HWENOU_EUNSUPPORTED
+    d1 = H.make_desc(1, "euler")
+    assert _create(d1, [H.make_inst((1 << 29) + 1, 1, (0, 1))])[0] == H.HWENOU_EUNSUPPORTED
+
+
 def test_calls_reject_null_handle():
     L = H.lib()
     assert L.hwenou_destroy(None) == H.HWENOU_EINVAL
