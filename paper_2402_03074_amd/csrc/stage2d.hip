@@ -223,7 +223,6 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
   double rcol[4];
   char_field<DIR, 0, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
   back_project<DIR, 0, TR>(C, rcol, Cc, true);
-  __builtin_amdgcn_sched_barrier(0);  // keep the fields apart: bounds register pressure
   {
     double lrow[4], r1[4];
     eig_row<DIR>(pr, 1, lrow, r1);
@@ -238,6 +237,8 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
     }
     back_project<DIR, 1, TR>(C1, r1, Cc, false);
   }
+  // scheduling barriers keep the later fields apart (bounds register pressure;
+  // without them the compiler spills to scratch)
   __builtin_amdgcn_sched_barrier(0);
   char_field<DIR, 2, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
   back_project<DIR, 2, TR>(C, rcol, Cc, false);
