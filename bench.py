@@ -37,10 +37,18 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 78.6
 # dt and finish kernels of one step (rocprofv3 kernel trace: ~5 us + ~4 us)
 AUX_US_PER_STEP = 9.0
-KERNEL_SOURCES = ["paper_2402_03074_amd/csrc/stage2d.hip",
-                  "paper_2402_03074_amd/csrc/hwenou_device.hpp",
+COMMON_SOURCES = ["paper_2402_03074_amd/csrc/hwenou_device.hpp",
                   "paper_2402_03074_amd/csrc/hwenou_internal.hpp"]
-COUNTERS_FILE = "profiles/stage2d_euler_2048_counters.md"
+KERNEL_SOURCES = ["paper_2402_03074_amd/csrc/stage2d.hip"] + COMMON_SOURCES
+# rocprofv3 counter summaries (profiles/) per stage kernel and the workload
+# they were taken on
+COUNTERS = {
+    2: ("stage2d_kernel", "profiles/stage2d_euler_2048_counters.md", "euler2d-2048",
+        KERNEL_SOURCES),
+    1: ("stage1d_kernel", "profiles/stage1d_euler_batch512_counters.md", "euler1d-batch512",
+        ["paper_2402_03074_amd/csrc/stage1d.hip"] + COMMON_SOURCES),
+}
+COUNTERS_FILE = COUNTERS[2][1]
 DEFAULT_WORKLOAD = "euler2d-2048"
 WORKLOADS = {
     "euler2d-2048": "2D Euler {n}x{n} periodic on [0,10]^2, seeded four-quadrant Riemann data "
@@ -59,22 +67,22 @@ DEFAULT_STEPS = {"euler2d-2048": 50, "advection1d-200": 1000, "euler1d-65536": 2
                  "euler1d-batch512": 200, "euler2d-batch64": 50}
 
 
-def kernel_source_hash():
+def kernel_source_hash(dim=2):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in COUNTERS[dim][3]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def recorded_counters():
-    """Per-launch figures recorded from rocprofv3 counter runs of this
-    benchmark (profiles/): algorithmic flops per cell-stage and calibrated
-    HBM bytes per launch, keyed by the kernel source hash they were taken on."""
+def recorded_counters(dim=2):
+    """Per-launch figures recorded from rocprofv3 counter runs of one
+    workload (profiles/): algorithmic flops per cell-stage and calibrated HBM
+    bytes per launch, keyed by the kernel source hash they were taken on."""
     out = {"source_sha256": None}
     try:
-        with open(os.path.join(ROOT, COUNTERS_FILE)) as fh:
+        with open(os.path.join(ROOT, COUNTERS[dim][1])) as fh:
             for line in fh:
                 if line.startswith("- ") and ":" in line:
                     k, v = line[2:].split(":", 1)
@@ -110,6 +118,8 @@ def parse():
     p.add_argument("--tune", action="store_true",
                    help="run the launch-shape autotuner first (default: the library's "
                         "occupancy-based launch shape; the batched workloads always tune)")
+    p.add_argument("--launch", default=None,
+                   help="fixed launch shape 'waves_per_cu,rows_per_item' instead of tuning")
     return p.parse_args()
 
 
@@ -159,12 +169,15 @@ def make_case(H, W, np, name, n=2048):
     raise ValueError(name)
 
 
-def run_case(H, torch, case, precision, steps, warmup, tune, char_decomp=True):
+def run_case(H, torch, case, precision, steps, warmup, tune, char_decomp=True, launch=None):
     S = H.Solver(case.dim, case.eq, case.insts, precision=precision, char_decomp=char_decomp,
                  **case.kw)
     ug = torch.tensor(case.u0, device="cuda")
     mg = torch.tensor(case.m0, device="cuda").to(S.mom_dtype)
-    launch = S.autotune(ug, mg) if tune else None
+    if launch is not None:
+        S.set_launch(*launch)
+    elif tune:
+        launch = S.autotune(ug, mg)
     # warm-up steps (untimed), then exactly `steps` timed steps
     if warmup > 0:
         S.advance(ug, mg, case.cfl, 1e30, warmup)
@@ -266,20 +279,25 @@ def mesh_difference(H, W, torch, np, n, t_final):
 
 
 def summary_roofline(case, r, precision, rec):
+    """Roofline position of the stage kernel: against the vector ALU peak
+    when its flops per cell-stage have been counted (both stage kernels are
+    bound by instruction issue), with the algorithmic HBM view beside it."""
     cells = case.cells
     kavg = r["stage_ms"]
+    kernel = COUNTERS[case.dim][0]
     byts = sum(stage_bytes(case.dim, case.ncomp, precision, s) for s in range(3)) / 3
     hbm = byts * cells / (kavg * 1e-3) / 1e9
-    if case.dim == 2 and case.eq == "euler":
-        flops = float(rec.get(f"algorithmic_flops_per_cell_stage_{precision}", "nan"))
+    hview = {"achieved_algorithmic": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": hbm / HBM_PEAK_GBS, "bytes_per_cell_stage": byts}
+    key = f"algorithmic_flops_per_cell_stage_{precision}"
+    if case.eq == "euler" and key in rec:
+        flops = float(rec[key])
         tf = flops * cells / (kavg * 1e-3) / 1e12
         return {"bound": "alu", "achieved": tf, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": tf / VALU_PEAK_TFLOPS, "kernel": "stage2d_kernel",
-                "avg_launch_ms": kavg, "flops_per_cell_stage": flops}, \
-            {"achieved_algorithmic": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-             "frac": hbm / HBM_PEAK_GBS, "bytes_per_cell_stage": byts}
+                "frac": tf / VALU_PEAK_TFLOPS, "kernel": kernel,
+                "avg_launch_ms": kavg, "flops_per_cell_stage": flops}, hview
     return {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": hbm / HBM_PEAK_GBS, "traffic": None, "kernel": "stage1d_kernel",
+            "frac": hbm / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
             "avg_launch_ms": kavg, "bytes_per_cell_stage": byts}, None
 
 
@@ -303,23 +321,25 @@ def main():
     print(f"[bench] generating {name}", file=sys.stderr, flush=True)
     case = make_case(H, W, np, name, n)
     tune = args.tune or name.endswith(("batch512", "batch64"))
+    fixed = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     results = {}
     for prec in precs:
         print(f"[bench] {prec}: {args.warmup} warm-up + {steps} timed steps",
               file=sys.stderr, flush=True)
-        results[prec] = r = run_case(H, torch, case, prec, steps, args.warmup, tune)
+        results[prec] = r = run_case(H, torch, case, prec, steps, args.warmup, tune,
+                                     launch=fixed)
         print(f"[bench] {prec}: {r['ms_per_step']:.3f} ms/step, stage {r['stage_ms']:.3f} ms",
               file=sys.stderr, flush=True)
 
-    rec = recorded_counters()
-    fresh = rec.get("source_sha256") == kernel_source_hash()
+    rec = recorded_counters(case.dim)
+    fresh = rec.get("source_sha256") == kernel_source_hash(case.dim)
     head = precs[0]
     r = results[head]
     roof, hbm = summary_roofline(case, r, head, rec)
     if roof["bound"] == "alu":
         roof["counters_current"] = fresh
         roof["traffic"] = (float(rec[f"hbm_bytes_per_launch_{head}"])
-                           if fresh and case.name == DEFAULT_WORKLOAD
+                           if fresh and case.name == COUNTERS[case.dim][2]
                            and f"hbm_bytes_per_launch_{head}" in rec else None)
     line = {
         "metric": METRIC if name == DEFAULT_WORKLOAD else "cell-stage updates/s",
@@ -376,7 +396,7 @@ def main():
                 "mixed_diff_over_mesh_diff": line["mixed_vs_fp64"]["l1_rho_diff"] / md})
     line["status"] = {p: results[p]["status"] for p in results}
     line["launch"] = {p: results[p]["launch"] for p in results}
-    line["kernel_source_sha256"] = kernel_source_hash()
+    line["kernel_source_sha256"] = kernel_source_hash(case.dim)
     line["copy_calibration_mib"] = copy_calibration(torch)
     if name == DEFAULT_WORKLOAD and not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
