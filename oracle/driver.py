@@ -30,7 +30,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 EQ = {"advection": 0, "burgers": 1, "euler": 2}
 WEIGHTS = {"scale_invariant": 0, "zq": 1, "linear": 2}
-BC = {"periodic": 0, "transmissive": 1}
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 ERR_NONPHYSICAL = 4
 
 
@@ -108,7 +108,8 @@ class Problem:
 
     dim: 1 or 2.  eq: 'advection' | 'burgers' | 'euler'.
     n: number of cells (1D) or (nx, ny) (2D).  domain: (a, b) or (a, b, c, d).
-    bc: 'periodic' | 'transmissive' or a tuple per side (x-lo, x-hi[, y-lo, y-hi]).
+    bc: 'periodic' | 'transmissive' | 'reflective' (Euler walls) or a tuple per side
+        (x-lo, x-hi[, y-lo, y-hi]).
     """
 
     def __init__(self, dim, eq, n, domain, bc="periodic", gas_gamma=1.4, adv=(1.0, 1.0),

@@ -39,6 +39,7 @@
 
 #define BC_PERIODIC 0
 #define BC_TRANSMISSIVE 1
+#define BC_REFLECTIVE 2
 
 #define ERR_NONPHYSICAL 4
 
@@ -92,10 +93,32 @@ void oracle_set_ops_2d(const double *M0, const double *MM, const double *G0,
 /* ------------------------------------------------------------------------ */
 /* helpers                                                                  */
 /* ------------------------------------------------------------------------ */
-static int wrap_index(int i, int n, int bc_lo, int bc_hi) {
-  if (i < 0) return bc_lo == BC_PERIODIC ? ((i % n) + n) % n : 0;
-  if (i >= n) return bc_hi == BC_PERIODIC ? i % n : n - 1;
+/* Source cell of index i of a grid of n cells (|overshoot| <= 2):
+ * periodic wrap, transmissive copy of the boundary cell, or reflective
+ * mirror image (-1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2).  *mirror is set
+ * to 1 for a mirror image. */
+static int bc_index(int i, int n, int bc_lo, int bc_hi, int *mirror) {
+  *mirror = 0;
+  if (i < 0) {
+    if (bc_lo == BC_PERIODIC) return ((i % n) + n) % n;
+    if (bc_lo == BC_REFLECTIVE) { *mirror = 1; return -1 - i; }
+    return 0;
+  }
+  if (i >= n) {
+    if (bc_hi == BC_PERIODIC) return i % n;
+    if (bc_hi == BC_REFLECTIVE) { *mirror = 1; return 2 * n - 1 - i; }
+    return n - 1;
+  }
   return i;
+}
+
+/* Euler data of a cell mirrored across a wall normal to direction d: the
+ * normal momentum (component 1 + d) changes sign, and a moment along d
+ * changes sign once more because its local coordinate does.  e is the
+ * moment direction, or -1 for the cell average. */
+static double mirror_sign(int k, int d, int e) {
+  const double s = k == 1 + d ? -1.0 : 1.0;
+  return e == d ? -s : s;
 }
 
 static double quad_form(const double *G, const double *c, int n) {
@@ -315,14 +338,18 @@ int oracle_rhs_1d(const oracle_params *P, int n, double dx, int bc_lo, int bc_hi
 #pragma omp parallel for schedule(static) reduction(| : bad)
   for (int e = 0; e < ne; ++e) {
     int i = e - 1;
-    int idx[3];
-    for (int d = -1; d <= 1; ++d) idx[d + 1] = wrap_index(i + d, n, bc_lo, bc_hi);
+    int idx[3], mir[3];
+    for (int d = -1; d <= 1; ++d) idx[d + 1] = bc_index(i + d, n, bc_lo, bc_hi, mir + d + 1);
+    /* sign of the average / moment of stencil cell t, component k */
+#define SU1(t, k) (mir[t] ? mirror_sign(k, 0, -1) : 1.0)
+#define SV1(t, k) (mir[t] ? mirror_sign(k, 0, 0) : 1.0)
     double *cp = pts + (size_t)e * 4 * nc;
     double *cv = vh + (size_t)e * nc;
     if (P->eq != EQ_EULER || !P->char_decomp) {
       for (int k = 0; k < nc; ++k) {
         const double *u = ubar + (size_t)k * n, *v = vbar + (size_t)k * n;
-        double s[5] = {u[idx[0]], u[idx[1]], u[idx[2]], v[idx[0]], v[idx[2]]};
+        double s[5] = {SU1(0, k) * u[idx[0]], SU1(1, k) * u[idx[1]], SU1(2, k) * u[idx[2]],
+                       SV1(0, k) * v[idx[0]], SV1(2, k) * v[idx[2]]};
         double p4[4];
         recon_1d_scalar(P, s, p4, cv + k);
         for (int G = 0; G < 4; ++G) cp[G * nc + k] = p4[G];
@@ -331,7 +358,7 @@ int oracle_rhs_1d(const oracle_params *P, int n, double dx, int bc_lo, int bc_hi
     }
     /* characteristic-wise: project the five stencil vectors with L(u_i) */
     double Ui[3], R[9], L[9];
-    for (int k = 0; k < 3; ++k) Ui[k] = ubar[(size_t)k * n + idx[1]];
+    for (int k = 0; k < 3; ++k) Ui[k] = SU1(1, k) * ubar[(size_t)k * n + idx[1]];
     if (euler_right_eigvecs(P, Ui, 1, 0, R) || invert(R, L, 3)) {
       bad |= 1;
       continue;
@@ -339,12 +366,14 @@ int oracle_rhs_1d(const oracle_params *P, int n, double dx, int bc_lo, int bc_hi
     double S[5][3];
     for (int k = 0; k < 3; ++k) {
       const double *u = ubar + (size_t)k * n, *v = vbar + (size_t)k * n;
-      S[0][k] = u[idx[0]];
-      S[1][k] = u[idx[1]];
-      S[2][k] = u[idx[2]];
-      S[3][k] = v[idx[0]];
-      S[4][k] = v[idx[2]];
+      S[0][k] = SU1(0, k) * u[idx[0]];
+      S[1][k] = SU1(1, k) * u[idx[1]];
+      S[2][k] = SU1(2, k) * u[idx[2]];
+      S[3][k] = SV1(0, k) * v[idx[0]];
+      S[4][k] = SV1(2, k) * v[idx[2]];
     }
+#undef SU1
+#undef SV1
     double Wp[4][3], Wv[3];
     for (int ch = 0; ch < 3; ++ch) {
       double s[5];
@@ -518,21 +547,28 @@ int oracle_rhs_2d(const oracle_params *P, int nx, int ny, double dx, double dy, 
       /* corner cells of the extended grid are never needed */
       if ((i < 0 || i >= nx) && (j < 0 || j >= ny)) continue;
       size_t at[10];
+      int mx[10], my[10];
       for (int lab = 1; lab <= 9; ++lab) {
         int a = (lab - 1) % 3 - 1, b = (lab - 1) / 3 - 1;
-        int ii = wrap_index(i + a, nx, bc[0], bc[1]);
-        int jj = wrap_index(j + b, ny, bc[2], bc[3]);
+        int ii = bc_index(i + a, nx, bc[0], bc[1], mx + lab);
+        int jj = bc_index(j + b, ny, bc[2], bc[3], my + lab);
         at[lab] = (size_t)jj * nx + ii;
       }
       cell2d *out = C + (size_t)ej * ex + ei;
-      /* gather data vectors per conserved component: DATA_2D order */
+      /* gather data vectors per conserved component: DATA_2D order; mirror
+       * images across x- and y-walls take the signs of mirror_sign() */
       double D[17][4];
       for (int k = 0; k < nc; ++k) {
-        for (int lab = 1; lab <= 9; ++lab) D[lab - 1][k] = ubar[k * plane + at[lab]];
+        for (int lab = 1; lab <= 9; ++lab)
+          D[lab - 1][k] = (mx[lab] ? mirror_sign(k, 0, -1) : 1.0) *
+                          (my[lab] ? mirror_sign(k, 1, -1) : 1.0) * ubar[k * plane + at[lab]];
         const int ml[4] = {2, 4, 6, 8};
         for (int t = 0; t < 4; ++t) {
-          D[9 + t][k] = vbar[k * plane + at[ml[t]]];
-          D[13 + t][k] = wbar[k * plane + at[ml[t]]];
+          const int lab = ml[t];
+          D[9 + t][k] = (mx[lab] ? mirror_sign(k, 0, 0) : 1.0) *
+                        (my[lab] ? mirror_sign(k, 1, 0) : 1.0) * vbar[k * plane + at[lab]];
+          D[13 + t][k] = (mx[lab] ? mirror_sign(k, 0, 1) : 1.0) *
+                         (my[lab] ? mirror_sign(k, 1, 1) : 1.0) * wbar[k * plane + at[lab]];
         }
       }
       int charwise = P->eq == EQ_EULER && P->char_decomp;

@@ -468,6 +468,76 @@ def test_mirror_symmetry_1d_euler():
     np.testing.assert_allclose(gh, (-mh * sgn_u[None])[:, :, ::-1], rtol=1e-12, atol=1e-12)
 
 
+def _mirror_x(u, m, axis_u, axis_m):
+    """Mirror image of Euler data across a wall normal to x (last axis):
+    order reversed, x-momentum negated, x-moments negated once more."""
+    sgn = np.ones(u.shape[0])
+    sgn[1] = -1.0
+    su = sgn.reshape((-1,) + (1,) * (u.ndim - 1))
+    um = np.flip(u * su, axis=axis_u)
+    sm = np.stack([-su, su])[: m.shape[0]] if m.shape[0] == 2 else (-su)[None]
+    mm = np.flip(m * sm, axis=axis_m)
+    return um, mm
+
+
+def test_reflective_walls_equal_mirror_extended_periodic_1d():
+    """Reflective walls at both ends of [0, 1] give the same right-hand side
+    and modified moments as the periodic problem on [0, 2] whose second half
+    is the mirror image of the first (the Euler equations are invariant under
+    x -> -x with the momentum negated)."""
+    n = 24
+    u, m = W.euler_1d_shocktube(n, seed=61)  # velocities up to 1 at the walls
+    um, mm = _mirror_x(u, m, 1, 2)
+    ue = np.concatenate([u, um], axis=1)
+    me = np.concatenate([m, mm], axis=2)
+    P = Problem(1, "euler", n, (0, 1), bc="reflective")
+    Pe = Problem(1, "euler", 2 * n, (0, 2), bc="periodic")
+    al = P.max_wavespeed(u)
+    assert np.array_equal(al, Pe.max_wavespeed(ue))
+    F1, Fm, mh = P.rhs(u, m, al)
+    G1, Gm, gh = Pe.rhs(ue, me, al)
+    scale = np.abs(F1).max()
+    assert np.abs(G1[:, :n] - F1).max() <= 1e-14 * scale
+    assert np.abs(Gm[:, :, :n] - Fm).max() <= 1e-14 * np.abs(Fm).max()
+    assert np.abs(gh[:, :, :n] - mh).max() <= 1e-14 * np.abs(mh).max()
+    # negative control: transmissive walls differ
+    T1, _, _ = Problem(1, "euler", n, (0, 1), bc="transmissive").rhs(u, m, al)
+    assert np.abs(T1 - F1).max() > 1e-3 * scale
+
+
+def test_reflective_walls_equal_mirror_extended_periodic_2d():
+    """2D: reflective walls on all four sides equal the periodic problem on
+    the domain doubled in x and y by mirror images (corner cells of the
+    stencils are mirrored in both directions)."""
+    n = 10
+    u, m = W.euler_2d_vortex_quadrant(n, seed=62, q=2)
+    perm = [0, 2, 1, 3]
+
+    def mirror_y(uu, mm_):  # mirror in y = transpose, mirror in x, transpose back
+        ut = uu[perm].transpose(0, 2, 1)
+        mt = mm_[::-1][:, perm].transpose(0, 1, 3, 2)
+        a, b = _mirror_x(ut, mt, 2, 3)
+        return a[perm].transpose(0, 2, 1), b[:, perm][::-1].transpose(0, 1, 3, 2)
+
+    ux, mx = _mirror_x(u, m, 2, 3)
+    uy, my = mirror_y(u, m)
+    uxy, mxy = mirror_y(ux, mx)
+    ue = np.concatenate([np.concatenate([u, ux], axis=2), np.concatenate([uy, uxy], axis=2)],
+                        axis=1)
+    me = np.concatenate([np.concatenate([m, mx], axis=3), np.concatenate([my, mxy], axis=3)],
+                        axis=2)
+    P = Problem(2, "euler", (n, n), (0, 10, 0, 10), bc="reflective")
+    Pe = Problem(2, "euler", (2 * n, 2 * n), (0, 20, 0, 20), bc="periodic")
+    al = P.max_wavespeed(u)
+    F1, Fm, mh = P.rhs(u, m, al)
+    G1, Gm, gh = Pe.rhs(np.ascontiguousarray(ue), np.ascontiguousarray(me), al)
+    assert np.abs(G1[:, :n, :n] - F1).max() <= 1e-14 * np.abs(F1).max()
+    assert np.abs(Gm[:, :, :n, :n] - Fm).max() <= 1e-14 * np.abs(Fm).max()
+    assert np.abs(gh[:, :, :n, :n] - mh).max() <= 1e-14 * np.abs(mh).max()
+    T1, _, _ = Problem(2, "euler", (n, n), (0, 10, 0, 10), bc="transmissive").rhs(u, m, al)
+    assert np.abs(T1 - F1).max() > 1e-3 * np.abs(F1).max()
+
+
 def test_transpose_symmetry_2d_euler():
     n = 10
     u, m = W.euler_2d_vortex_quadrant(n, seed=32, q=2)
