@@ -1,0 +1,86 @@
+"""Pins of the oracle on the 1D shock problems of Section 3.2.
+
+The paper shows these problems only as figures (not reproduced here), so the
+oracle is pinned against what the mathematics fixes: the exact solution of
+the Lax Riemann problem (a textbook exact Riemann solver, itself checked
+against the Rankine-Hugoniot conditions), convergence towards it under mesh
+refinement, positivity through the final times (the paper runs these
+problems without a positivity limiter), and conservation of mass and energy
+between reflective walls.
+"""
+import numpy as np
+import pytest
+
+from oracle.driver import Problem
+import workloads as W
+
+G = 1.4
+
+
+def _cons(rho, u, p):
+    return rho, rho * u, p / (G - 1.0) + 0.5 * rho * u * u
+
+
+def test_exact_riemann_solver_satisfies_jump_conditions():
+    """Sod's problem: the star state is the tabulated one (p* = 0.30313,
+    u* = 0.92745), and the three Rankine-Hugoniot conditions hold across the
+    right shock with one shock speed."""
+    L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    xi = np.linspace(-1.5, 1.8, 33001)
+    rho, u, p = W.riemann_exact(L, R, xi)
+    mid = np.argmin(np.abs(xi - 0.93 * 0.5))  # between the contact and the shock
+    assert abs(p[mid] - 0.30313) < 5e-6 and abs(u[mid] - 0.92745) < 5e-6
+    # states on either side of the right shock
+    k = np.nonzero(np.abs(np.diff(rho)) > 1e-3)[0][-1]
+    a = _cons(rho[k - 1], u[k - 1], p[k - 1])
+    b = _cons(rho[k + 2], u[k + 2], p[k + 2])
+    S = (a[1] - b[1]) / (a[0] - b[0])  # from the mass condition
+    assert xi[k - 1] < S < xi[k + 2]
+    flux = lambda q, pp, uu: (q[1], q[1] * uu + pp, (q[2] + pp) * uu)
+    fa, fb = flux(a, p[k - 1], u[k - 1]), flux(b, p[k + 2], u[k + 2])
+    for c in range(3):
+        assert abs((fa[c] - fb[c]) - S * (a[c] - b[c])) < 1e-10
+
+
+def test_exact_riemann_solver_matches_lax_structure():
+    """Lax problem: left rarefaction, contact, right shock; the far states are
+    the initial states."""
+    L, R = W.LAX_STATES
+    rho, u, p = W.riemann_exact(L, R, np.array([-10.0, 10.0]))
+    assert np.allclose([rho[0], u[0], p[0]], L) and np.allclose([rho[1], u[1], p[1]], R)
+
+
+def _lax_l1(n):
+    _, dom, bc, T = W.SHOCK_SUITE_1D["lax"]
+    u, m = W.shock_suite_1d("lax", n)
+    P = Problem(1, "euler", n, dom, bc=bc)
+    uf, _, t, _ = P.advance(u, m, 0.6, T)
+    assert abs(t - T) < 1e-14
+    ex = W.riemann_exact_averages(*W.LAX_STATES, n, dom[0], dom[1], 0.0, T)
+    return np.abs(uf[0] - ex).mean()
+
+
+def test_oracle_lax_converges_to_exact_solution():
+    """The L1 density error against the exact solution falls under mesh
+    refinement at the rate of a shock-capturing scheme (first order at the
+    discontinuities: ratio near 2 per halving)."""
+    e = [_lax_l1(n) for n in (200, 400, 800)]  # measured 7.1e-3, 3.5e-3, 1.8e-3
+    assert e[0] < 1.0e-2
+    assert e[0] / e[1] > 1.6 and e[1] / e[2] > 1.6, e
+
+
+@pytest.mark.parametrize("name", list(W.SHOCK_SUITE_1D))
+def test_oracle_shock_suite_stays_physical(name):
+    """Every problem reaches its final time with positive density and
+    pressure (the oracle raises otherwise).  Between the reflective walls of
+    the blast-wave problem, and in the Sedov problem (whose waves stay away
+    from the boundaries), total mass and energy are conserved to rounding."""
+    n, dom, bc, T = W.SHOCK_SUITE_1D[name]
+    u, m = W.shock_suite_1d(name)
+    P = Problem(1, "euler", n, dom, bc=bc)
+    uf, _, t, steps = P.advance(u, m, 0.6, T)
+    assert abs(t - T) < 1e-14 * max(T, 1.0) and steps > 10
+    assert P.check_physical(uf)
+    if name in ("blast", "sedov"):
+        for k in (0, 2):
+            assert abs(uf[k].sum() - u[k].sum()) <= 1e-12 * np.abs(u[k]).sum()

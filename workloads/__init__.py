@@ -178,6 +178,132 @@ def euler_1d_riemann(n, left, right, x0, a, b, gas_gamma=GAS_GAMMA):
     return ubar, np.zeros((1,) + ubar.shape)
 
 
+def _piecewise_prim(n, a, b, pieces, gas_gamma=GAS_GAMMA):
+    """Cell data of piecewise-constant primitive states (rho, u, p) with every
+    jump on a cell face: pieces = [(x_end, (rho, u, p)), ...]."""
+    xc = a + (np.arange(n) + 0.5) * (b - a) / n
+    st = np.empty((3, n))
+    lo = a
+    for x_end, prim in pieces:
+        sel = (xc > lo) & (xc < x_end)
+        st[:, sel] = np.array(prim, dtype=np.float64)[:, None]
+        lo = x_end
+    ubar = prim_to_cons(st[0], [st[1]], st[2], gas_gamma)
+    return ubar, np.zeros((1,) + ubar.shape)
+
+
+# 1D shock problems of Section 3.2: name -> (cells, domain, boundary, final time)
+SHOCK_SUITE_1D = {
+    "lax": (200, (-0.5, 0.5), "transmissive", 0.16),
+    "blast": (800, (0.0, 1.0), "reflective", 0.038),
+    "shu_osher": (400, (-5.0, 5.0), "transmissive", 1.8),
+    "double_rarefaction": (400, (-1.0, 1.0), "transmissive", 0.6),
+    "sedov": (801, (-2.0, 2.0), "transmissive", 0.001),
+}
+LAX_STATES = ((0.445, 0.698, 3.528), (0.5, 0.0, 0.571))
+
+
+def shock_suite_1d(name, n=None):
+    """Initial cell averages and moments of a 1D shock problem of Section 3.2
+    (Lax, interacting blast waves, Shu-Osher, double rarefaction, Sedov).
+    The Sedov problem puts the energy 3.2e6 / dx into the centre cell of an
+    odd number of cells (801; the paper's 800 cells have no centre cell)."""
+    n0, (a, b), _, _ = SHOCK_SUITE_1D[name]
+    n = n0 if n is None else n
+    if name == "lax":
+        return _piecewise_prim(n, a, b, [(0.0, LAX_STATES[0]), (b, LAX_STATES[1])])
+    if name == "blast":
+        return _piecewise_prim(n, a, b, [(0.1, (1.0, 0.0, 1000.0)), (0.9, (1.0, 0.0, 0.01)),
+                                         (b, (1.0, 0.0, 100.0))])
+    if name == "double_rarefaction":
+        return _piecewise_prim(n, a, b, [(0.0, (7.0, -1.0, 0.2)), (b, (7.0, 1.0, 0.2))])
+    if name == "shu_osher":
+        def f(X):
+            left = X < -4.0
+            rho = np.where(left, 3.857143, 1.0 + 0.2 * np.sin(5.0 * X))
+            u = np.where(left, 2.629369, 0.0)
+            p = np.where(left, 10.333333, 1.0)
+            return prim_to_cons(rho, [u], p)
+        return cell_moments_1d(f, a, b, n)
+    if name == "sedov":
+        assert n % 2 == 1, "the Sedov problem needs a centre cell"
+        dx = (b - a) / n
+        ubar = np.zeros((3, n))
+        ubar[0] = 1.0
+        ubar[2] = 1e-12
+        ubar[2, n // 2] = 3200000.0 / dx
+        return ubar, np.zeros((1, 3, n))
+    raise ValueError(name)
+
+
+def riemann_exact(left, right, xi, gas_gamma=GAS_GAMMA, tol=1e-14):
+    """Exact solution of the 1D Euler Riemann problem (primitive states
+    (rho, u, p) left and right of x = 0) at similarity coordinates
+    xi = x / t: the star pressure from Newton's method on the pressure
+    function, then sampling of the wave pattern (two shocks or rarefactions
+    around a contact; no vacuum).  Returns rho, u, p arrays."""
+    g = gas_gamma
+    rl, ul, pl = left
+    rr, ur, pr = right
+    cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
+    assert 2.0 / (g - 1.0) * (cl + cr) > ur - ul, "vacuum is generated"
+
+    def fk(p, rk, pk, ck):
+        if p > pk:  # shock
+            A, B = 2.0 / ((g + 1.0) * rk), (g - 1.0) / (g + 1.0) * pk
+            q = math.sqrt(A / (p + B))
+            return (p - pk) * q, q * (1.0 - 0.5 * (p - pk) / (p + B))
+        r = (p / pk) ** ((g - 1.0) / (2.0 * g))  # rarefaction
+        return 2.0 * ck / (g - 1.0) * (r - 1.0), r / (rk * ck)
+
+    p = max(1e-12, 0.5 * (pl + pr) - 0.125 * (ur - ul) * (rl + rr) * (cl + cr))
+    for _ in range(100):
+        f1, d1 = fk(p, rl, pl, cl)
+        f2, d2 = fk(p, rr, pr, cr)
+        dp = (f1 + f2 + ur - ul) / (d1 + d2)
+        p_new = max(p - dp, 1e-14)
+        if abs(p_new - p) <= tol * (p_new + p):
+            p = p_new
+            break
+        p = p_new
+    us = 0.5 * (ul + ur) + 0.5 * (fk(p, rr, pr, cr)[0] - fk(p, rl, pl, cl)[0])
+    xi = np.asarray(xi, dtype=np.float64)
+    rho, u, pp = np.empty_like(xi), np.empty_like(xi), np.empty_like(xi)
+    for side, (rk, uk, pk, ck, sgn) in enumerate(((rl, ul, pl, cl, -1.0), (rr, ur, pr, cr, 1.0))):
+        sel = xi <= us if side == 0 else xi > us
+        x = xi[sel]
+        if p > pk:  # shock moving away from the contact
+            rs = rk * ((p / pk + (g - 1.0) / (g + 1.0)) / ((g - 1.0) / (g + 1.0) * p / pk + 1.0))
+            S = uk + sgn * ck * math.sqrt((g + 1.0) / (2.0 * g) * p / pk + (g - 1.0) / (2.0 * g))
+            out = sgn * (x - S) > 0
+            rho[sel] = np.where(out, rk, rs)
+            u[sel] = np.where(out, uk, us)
+            pp[sel] = np.where(out, pk, p)
+        else:  # rarefaction fan
+            rs = rk * (p / pk) ** (1.0 / g)
+            cs = ck * (p / pk) ** ((g - 1.0) / (2.0 * g))
+            head, tail = uk + sgn * ck, us + sgn * cs
+            r_out = sgn * (x - head) > 0
+            r_in = sgn * (x - tail) < 0
+            fan_u = 2.0 / (g + 1.0) * (-sgn * ck + (g - 1.0) / 2.0 * uk + x)
+            fan_c = sgn * (fan_u - x)
+            fan_rho = rk * np.abs(fan_c / ck) ** (2.0 / (g - 1.0))
+            fan_p = pk * np.abs(fan_c / ck) ** (2.0 * g / (g - 1.0))
+            rho[sel] = np.where(r_out, rk, np.where(r_in, rs, fan_rho))
+            u[sel] = np.where(r_out, uk, np.where(r_in, us, fan_u))
+            pp[sel] = np.where(r_out, pk, np.where(r_in, p, fan_p))
+    return rho, u, pp
+
+
+def riemann_exact_averages(left, right, n, a, b, x0, t, samples=64, gas_gamma=GAS_GAMMA):
+    """Cell averages of the exact Riemann density at time t (midpoint rule
+    with `samples` points per cell)."""
+    dx = (b - a) / n
+    x = a + (np.arange(n)[:, None] + (np.arange(samples)[None, :] + 0.5) / samples) * dx
+    rho, _, _ = riemann_exact(left, right, (x - x0) / t, gas_gamma)
+    return rho.mean(axis=1)
+
+
 # ----------------------------------------------------------------------------
 # 2D workloads
 # ----------------------------------------------------------------------------
