@@ -57,7 +57,12 @@ enum { HWENOU_FP64 = 0, HWENOU_MIXED = 1 };
 /* nonlinear weights: scale-invariant (Eq. (2.8)/(2.14)), the scale-dependent
  * original (u_ave = 1, Remark 2.1 of Section 2.1), or linear (w = gamma). */
 enum { HWENOU_W_SCALE_INVARIANT = 0, HWENOU_W_ZQ = 1, HWENOU_W_LINEAR = 2 };
-enum { HWENOU_BC_PERIODIC = 0, HWENOU_BC_TRANSMISSIVE = 1 };
+/* boundary conditions per side: periodic; transmissive (outflow: ghost cells
+ * copy the boundary cell); reflective (Euler only: a solid wall, ghost cells
+ * are mirror images with the wall-normal momentum negated and the moments
+ * along the wall normal negated once more), the walls of the blast-wave and
+ * Sedov problems of Section 3.2. */
+enum { HWENOU_BC_PERIODIC = 0, HWENOU_BC_TRANSMISSIVE = 1, HWENOU_BC_REFLECTIVE = 2 };
 
 /* Scheme description. */
 typedef struct hwenou_desc {
@@ -75,8 +80,8 @@ typedef struct hwenou_desc {
 } hwenou_desc;
 
 /* One instance: a uniform grid of nx x ny cells on [x0, x1] x [y0, y1]
- * (ny = 1, y0/y1 ignored in 1D).  bc: x-lo, x-hi, y-lo, y-hi.  Transmissive
- * ghost cells copy the average and moments of the boundary cell. */
+ * (ny = 1, y0/y1 ignored in 1D).  bc: x-lo, x-hi, y-lo, y-hi (HWENOU_BC_*).
+ * Transmissive ghost cells copy the average and moments of the boundary cell. */
 typedef struct hwenou_inst {
   int nx, ny;
   double x0, x1, y0, y1;
@@ -92,9 +97,9 @@ typedef struct hwenou_handle hwenou_handle;
  * hwenou_advance, the stored modified moments of stage 0, per-instance
  * alpha/dt/t/step arrays and the work lists.  Errors: EINVAL (dim, eq,
  * precision or weights out of range; n_inst < 1; nx or ny < 3; overlapping
- * instances; gas_gamma <= 1 for Euler), EUNSUPPORTED (an instance of more than
- * 2^29 cells: the kernels address an instance with 32-bit byte offsets),
- * ENOMEM, EHIP.  On error *out is NULL. */
+ * instances; gas_gamma <= 1 for Euler; a reflective side for a scalar law),
+ * EUNSUPPORTED (an instance of more than 2^29 cells: the kernels address an
+ * instance with 32-bit byte offsets), ENOMEM, EHIP.  On error *out is NULL. */
 int hwenou_create(const hwenou_desc* desc, int n_inst, const hwenou_inst* inst, void* stream,
                   hwenou_handle** out);
 

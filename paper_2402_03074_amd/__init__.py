@@ -26,7 +26,7 @@ HWENOU_OK, HWENOU_EINVAL, HWENOU_ENOMEM, HWENOU_EHIP, HWENOU_ENONPHYSICAL, \
 EQ = {"advection": 0, "burgers": 1, "euler": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 WEIGHTS = {"scale_invariant": 0, "zq": 1, "linear": 2}
-BC = {"periodic": 0, "transmissive": 1}
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 
 EXPORTS = ["hwenou_create", "hwenou_destroy", "hwenou_strerror", "hwenou_max_wavespeed",
            "hwenou_stage", "hwenou_advance", "hwenou_status", "hwenou_set_launch",

@@ -305,7 +305,8 @@ int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, voi
     if (I.nx < 3 || (d->dim == 2 && ny < 3)) return HWENOU_EINVAL;
     if (!(I.x1 > I.x0) || (d->dim == 2 && !(I.y1 > I.y0))) return HWENOU_EINVAL;
     for (int s = 0; s < 2 * d->dim; ++s)
-      if (I.bc[s] != HWENOU_BC_PERIODIC && I.bc[s] != HWENOU_BC_TRANSMISSIVE)
+      if (I.bc[s] != HWENOU_BC_PERIODIC && I.bc[s] != HWENOU_BC_TRANSMISSIVE &&
+          !(I.bc[s] == HWENOU_BC_REFLECTIVE && d->eq == HWENOU_EQ_EULER))
         return HWENOU_EINVAL;
     if (I.offset < 0) return HWENOU_EINVAL;
     const long long n = (long long)I.nx * ny;

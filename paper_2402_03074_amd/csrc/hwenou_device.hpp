@@ -25,7 +25,7 @@ namespace hwenou {
 
 enum : int { EQ_ADVECTION = 0, EQ_BURGERS = 1, EQ_EULER = 2 };
 enum : int { W_SCALE_INVARIANT = 0, W_ZQ = 1, W_LINEAR = 2 };
-enum : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
+enum : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 
 // Gauss points on [-1/2, 1/2]: 3-point Gauss (sqrt(15)/10, weights 5/18, 4/9)
 // and 4-point Gauss-Lobatto (1/2, sqrt(5)/10, weights 1/12, 5/12).
@@ -47,10 +47,40 @@ struct SchemeParams {
   int weights;          // W_*
 };
 
-__device__ __forceinline__ int wrap_index(int i, int n, int bc_lo, int bc_hi) {
-  if (i < 0) return bc_lo == BC_PERIODIC ? (i + n) : 0;  // |i| <= 2 <= n for periodic
-  if (i >= n) return bc_hi == BC_PERIODIC ? (i - n) : n - 1;
+// Source cell of index i of a grid of n >= 3 cells, -3 <= i <= n + 2:
+// periodic wrap, transmissive copy of the boundary cell, or the mirror image
+// at a reflective wall (-1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2, n+2 -> n-3),
+// flagged in `mirrored`.
+__device__ __forceinline__ int bc_index(int i, int n, int bc_lo, int bc_hi, bool& mirrored) {
+  mirrored = false;
+  if (i < 0) {
+    if (bc_lo == BC_PERIODIC) return i + n;
+    mirrored = bc_lo == BC_REFLECTIVE;
+    return mirrored ? -1 - i : 0;
+  }
+  if (i >= n) {
+    if (bc_hi == BC_PERIODIC) return i - n;
+    mirrored = bc_hi == BC_REFLECTIVE;
+    return mirrored ? 2 * n - 1 - i : n - 1;
+  }
   return i;
+}
+__device__ __forceinline__ int wrap_index(int i, int n, int bc_lo, int bc_hi) {
+  bool m;
+  return bc_index(i, n, bc_lo, bc_hi, m);
+}
+
+// Euler data of a cell mirrored across a wall normal to direction D
+// (reflective boundary): the normal momentum (component 1 + D) changes sign,
+// and the moments along D change sign once more because their local
+// coordinate does.  u: averages [NC]; m: moments [dim][NC] (m[0] along x).
+template <int D, int NC, class T, class TM>
+__device__ __forceinline__ void mirror_cell(T (&u)[NC], TM (*m)[NC], int dim) {
+  u[1 + D] = -u[1 + D];
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+    if (k != 1 + D) m[D][k] = -m[D][k];
+  if (dim == 2) m[1 - D][1 + D] = -m[1 - D][1 + D];
 }
 
 // Global memory access through a wave-uniform base pointer (row and

@@ -37,9 +37,11 @@ __global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
     // its right neighbour from the next lane; lanes further right are unused
     if (i > n + 1) i = n + 1;
     const bool owner = lane >= 1 && lane <= kStripWidth && i < n;
-    const int im = wrap_index(i - 1, n, I.bc[0], I.bc[1]);
-    const int ic = wrap_index(i, n, I.bc[0], I.bc[1]);
-    const int ip = wrap_index(i + 1, n, I.bc[0], I.bc[1]);
+    bool mir_m, mir_c, mir_p;  // mirror images at reflective walls
+    const int im = bc_index(i - 1, n, I.bc[0], I.bc[1], mir_m);
+    const int ic = bc_index(i, n, I.bc[0], I.bc[1], mir_c);
+    const int ip = bc_index(i + 1, n, I.bc[0], I.bc[1], mir_p);
+    const bool walls = EQ == EQ_EULER && (I.bc[0] == BC_REFLECTIVE || I.bc[1] == BC_REFLECTIVE);
     const double* u = A.u_in + I.offset;
     const TM* m = A.m_in + I.offset;
     const long long o = I.offset + i;
@@ -68,6 +70,13 @@ __global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
       for (int k = 0; k < NC; ++k) {
         Uend[k] = u[k * plane + ie];
         Vend[k] = m[k * plane + ie];
+      }
+    }
+    if constexpr (EQ == EQ_EULER) {
+      if (walls) {
+        if (mir_c) mirror_cell<0, NC>(Uc, reinterpret_cast<TM(*)[NC]>(Vc), 1);
+        if ((edge_lo && mir_m) || (edge_hi && mir_p))
+          mirror_cell<0, NC>(Uend, reinterpret_cast<TM(*)[NC]>(Vend), 1);
       }
     }
 #pragma unroll

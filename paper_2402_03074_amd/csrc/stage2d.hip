@@ -285,6 +285,8 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
     // grid columns of the LDS columns this lane loads (clamped, then wrapped)
     const int gx0 = wrap_index(min(c0 - 2 + lane, nx + 1), nx, I.bc[0], I.bc[1]);
     const int gx1 = wrap_index(min(c0 + 62 + lane, nx + 1), nx, I.bc[0], I.bc[1]);
+    const bool walls = EQ == EQ_EULER && (I.bc[0] == BC_REFLECTIVE || I.bc[1] == BC_REFLECTIVE ||
+                                          I.bc[2] == BC_REFLECTIVE || I.bc[3] == BC_REFLECTIVE);
     const bool extra = lane < 2;
     const unsigned o0u = (unsigned)gx0 * 8u, o0m = (unsigned)gx0 * (unsigned)sizeof(TM);
     const unsigned o1u = (unsigned)gx1 * 8u, o1m = (unsigned)gx1 * (unsigned)sizeof(TM);
@@ -310,7 +312,41 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
         }
       }
     };
-    auto store = [&](int slot) {
+    // Reflective walls: the stored cells of grid row `row` that are mirror
+    // images (ghost columns beyond an x-wall, or the whole row beyond a
+    // y-wall) get the signs of the mirror image: the wall-normal momentum
+    // and the moments along the wall normal change sign (twice for the x-
+    // moment of the x-momentum and the y-moment of the y-momentum).  Runs
+    // after the row is in LDS, outside the register-heavy part of the row.
+    auto mirror_row = [&](int slot, int row) {
+      const bool my = (row < 0 && I.bc[2] == BC_REFLECTIVE) ||
+                      (row >= ny && I.bc[3] == BC_REFLECTIVE);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        if (e == 1 && !extra) break;
+        const int c = e == 0 ? c0 - 2 + lane : c0 + 62 + lane;  // grid column
+        const bool mx = (c < 0 && I.bc[0] == BC_REFLECTIVE) ||
+                        (c >= nx && I.bc[1] == BC_REFLECTIVE);
+        if (!(mx || my)) continue;
+        const int l = e == 0 ? lane : 64 + lane;
+        double uu[NC], mm[2][NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          uu[k] = B.u[slot][k][l];
+          mm[0][k] = B.m[slot][0][k][l];
+          mm[1][k] = B.m[slot][1][k][l];
+        }
+        if (mx) mirror_cell<0, NC>(uu, mm, 2);
+        if (my) mirror_cell<1, NC>(uu, mm, 2);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          B.u[slot][k][l] = uu[k];
+          B.m[slot][0][k][l] = mm[0][k];
+          B.m[slot][1][k][l] = mm[1][k];
+        }
+      }
+    };
+    auto store = [&](int slot, int row) {
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
         B.u[slot][k][lane] = pu0[k];
@@ -322,6 +358,9 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
           B.m[slot][1][k][64 + lane] = (double)pm1[1][k];
         }
       }
+      if constexpr (EQ == EQ_EULER) {
+        if (walls) mirror_row(slot, row);
+      }
     };
     auto slot_of = [](int row) { return ((row % 3) + 3) % 3; };
 
@@ -329,7 +368,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
     // prologue: rows r0-2 .. r0 into LDS, r0+1 into registers
     for (int row = r0 - 2; row <= r0; ++row) {
       fetch(row);
-      store(slot_of(row));
+      store(slot_of(row), row);
     }
     fetch(r0 + 1);
     __syncthreads();
@@ -548,7 +587,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 
       // ---- advance the LDS ring: row j+2 from registers, prefetch j+3 ----
       __syncthreads();
-      if (j + 2 <= r1 + 1) store(slot_of(j + 2));
+      if (j + 2 <= r1 + 1) store(slot_of(j + 2), j + 2);
       if (j + 3 <= r1 + 1) fetch(j + 3);
       __syncthreads();
     }

@@ -67,6 +67,15 @@ def test_create_rejects_bad_instances():
         H.HWENOU_EINVAL
 
 
+def test_create_rejects_reflective_scalar_law():
+    """Reflective walls are defined for the Euler equations only."""
+    d = H.make_desc(1, "advection")
+    assert _create(d, [H.make_inst(10, 1, (0, 1), "reflective")])[0] == H.HWENOU_EINVAL
+    d2 = H.make_desc(2, "burgers")
+    inst = H.make_inst(10, 10, (0, 1, 0, 1), ("periodic", "periodic", "reflective"))
+    assert _create(d2, [inst])[0] == H.HWENOU_EINVAL
+
+
 def test_create_rejects_oversized_instance():
     """An instance of more than 2^29 cells is refused before any device call:
     the kernels address an instance with 32-bit byte offsets."""
