@@ -29,11 +29,17 @@ SOURCE_FLAGS = {"stage2d.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"
 
 def _compile(src, verbose, extra):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ([HIPCC] + FLAGS + SOURCE_FLAGS.get(src, []) + extra +
-           ["-c", os.path.join(CSRC, src), "-o", obj])
+    base = [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = base[:1] + SOURCE_FLAGS.get(src, []) + base[1:]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and SOURCE_FLAGS.get(src):
+        # the scheduler is experimental: fall back to the default one (same
+        # results, somewhat slower) rather than fail the build
+        print(f"warning: {src} failed with {' '.join(SOURCE_FLAGS[src])}; "
+              "building it with the default scheduler", file=sys.stderr)
+        r = subprocess.run(base, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     out = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l
