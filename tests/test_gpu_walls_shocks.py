@@ -191,3 +191,36 @@ def test_shock_suite_to_final_time(name):
         e_gpu = np.abs(ug[0] - ex).mean()
         print(f"[gpu]   lax L1 density error vs exact: {e_gpu:.3e}", flush=True)
         assert e_gpu < 1.0e-2
+
+
+def test_scaled_lax_problem_on_gpu():
+    """The scale demonstration of Section 3.2 on the HIP path: with data
+    (zeta rho, u, zeta p), zeta = 1e6, the scale-invariant weights keep the
+    density within 1e-3 (L1, relative) of zeta times the unscaled solution,
+    the scale-dependent (ZQ) weights deviate by more than five times as much,
+    and the GPU's scaled scale-invariant run matches the oracle's."""
+    n, dom, bc, T = W.SHOCK_SUITE_1D["lax"]
+    u0, m0 = W.shock_suite_1d("lax")
+    zeta = 1e6
+    dev = {}
+    for weights in ("scale_invariant", "zq"):
+        print(f"[gpu] scaled Lax problem, {weights} weights", flush=True)
+        P = Problem(1, "euler", n, dom, bc=bc, weights=weights)
+        (u1, _), _, _, st1 = _gpu_run(P, u0, m0, T, "fp64")
+        (uz, _), _, _, stz = _gpu_run(P, zeta * u0, zeta * m0, T, "fp64")
+        assert st1 == 0 and stz == 0
+        dev[weights] = float(np.abs(uz[0] / zeta - u1[0]).mean() / np.abs(u1[0]).mean())
+        if weights == "scale_invariant":
+            # near-flat regions sit at the epsilon threshold of the weights
+            # at this scale, so the bar is again the oracle's own one-ulp
+            # sensitivity (times ten)
+            uo, _, _, _ = P.advance(zeta * u0, zeta * m0, 0.6, T)
+            up, _, _, _ = P.advance(np.nextafter(zeta * u0, np.inf), zeta * m0, 0.6, T)
+            sens = _l1rel(up[0], uo[0])
+            err = _l1rel(uz[0], uo[0])
+            print(f"[gpu]   scaled run vs oracle {err:.2e}, oracle sensitivity {sens:.2e}",
+                  flush=True)
+            assert err <= max(1e-10, 10.0 * sens)
+    print(f"[gpu]   deviation from zeta * unscaled: {dev}", flush=True)
+    assert dev["scale_invariant"] < 1e-3 < dev["zq"]
+    assert dev["zq"] > 5.0 * dev["scale_invariant"]
