@@ -429,6 +429,21 @@ __device__ __forceinline__ void lf_flux(const SchemeParams& P, const T (&um)[NC]
 }
 
 // wave speeds |f'(u)| (x) and |g'(u)| (y) of a cell average, and validity
+// Physical-state check without the wave speeds: finite values and, for
+// Euler, rho > 0 and p > 0, with p > 0 tested as rho E - |m|^2 / 2 > 0 (the
+// same condition for rho > 0, free of the division and square root).
+template <int EQ, int NC>
+__device__ __forceinline__ bool physical_state(const double (&U)[NC]) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) ok = ok && isfinite(U[k]);
+  if constexpr (EQ == EQ_EULER) {
+    const double m2 = U[1] * U[1] + (NC == 4 ? U[2] * U[2] : 0.0);
+    ok = ok && U[0] > 0.0 && U[0] * U[NC - 1] - 0.5 * m2 > 0.0;
+  }
+  return ok;
+}
+
 template <int EQ, int NC>
 __device__ __forceinline__ bool wave_speeds(const SchemeParams& P, const double (&U)[NC], double& sx,
                                             double& sy) {

@@ -203,7 +203,12 @@ __global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
     }
     double sx = 0.0, sy = 0.0;
     bool ok = true;
-    if (owner) ok = wave_speeds<EQ, NC>(P, Uo, sx, sy);
+    if (owner) {
+      if (A.alpha_next != nullptr)  // the wave speeds feed the next step's alpha
+        ok = wave_speeds<EQ, NC>(P, Uo, sx, sy);
+      else
+        ok = physical_state<EQ, NC>(Uo);
+    }
     if (!ok) atomicOr(A.status, 1);
     if (A.alpha_next != nullptr) {
       const double mx = wave_max(owner ? sx : 0.0);
