@@ -341,6 +341,13 @@ def main():
         roof["traffic"] = (float(rec[f"hbm_bytes_per_launch_{head}"])
                            if fresh and case.name == COUNTERS[case.dim][2]
                            and f"hbm_bytes_per_launch_{head}" in rec else None)
+        if roof["traffic"] is not None and hbm is not None:
+            # measured HBM rate: calibrated FETCH_SIZE + WRITE_SIZE per launch
+            # over the launch time of this run
+            meas = roof["traffic"] / (roof["avg_launch_ms"] * 1e-3) / 1e9
+            hbm["achieved_measured"] = meas
+            hbm["frac_measured"] = meas / HBM_PEAK_GBS
+            hbm["measured_over_algorithmic"] = meas / hbm["achieved_algorithmic"]
     line = {
         "metric": METRIC if name == DEFAULT_WORKLOAD else "cell-stage updates/s",
         "value": r["rate"],
