@@ -103,6 +103,15 @@ def _ptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def _char_mode(c):
+    """True / 1: direction-split characteristic sweeps; False / 0:
+    component-wise; 2 or 'single': one x-characteristic reconstruction for
+    both directions."""
+    if c == "single":
+        return 2
+    return int(c)
+
+
 class Problem:
     """A single HWENO-U problem on a uniform periodic/transmissive grid.
 
@@ -110,6 +119,9 @@ class Problem:
     n: number of cells (1D) or (nx, ny) (2D).  domain: (a, b) or (a, b, c, d).
     bc: 'periodic' | 'transmissive' | 'reflective' (Euler walls) or a tuple per side
         (x-lo, x-hi[, y-lo, y-hi]).
+    char_decomp (Euler): True / 1 direction-split characteristic sweeps (the
+        default), False / 0 component-wise, 2 / 'single' one reconstruction in
+        x-characteristic variables for every output (2D).
     """
 
     def __init__(self, dim, eq, n, domain, bc="periodic", gas_gamma=1.4, adv=(1.0, 1.0),
@@ -130,7 +142,7 @@ class Problem:
             bc = (bc,) * (2 * dim)
         self.bc = tuple(BC[b] for b in bc)
         self.ncomp = 1 if eq != "euler" else dim + 2
-        self.params = _Params(EQ[eq], self.ncomp, WEIGHTS[weights], int(bool(char_decomp)),
+        self.params = _Params(EQ[eq], self.ncomp, WEIGHTS[weights], _char_mode(char_decomp),
                               float(adv[0]), float(adv[1] if len(adv) > 1 else 0.0),
                               float(gas_gamma), float(gamma_low), float(eps))
 

@@ -47,7 +47,10 @@ typedef struct {
   int eq;          /* EQ_* */
   int ncomp;       /* 1 for scalar laws; 3 (1D) or 4 (2D) for Euler */
   int weights;     /* W_* */
-  int char_decomp; /* Euler: 1 = characteristic-wise, 0 = component-wise */
+  int char_decomp; /* Euler: 0 = component-wise; 1 = characteristic-wise, the
+                      x-sweep in x-characteristic variables, the y-sweep in
+                      y-characteristic variables; 2 = characteristic-wise with
+                      the single x-projection for every output (2D) */
   double adv_x, adv_y;   /* advection velocity */
   double gas_gamma;      /* ratio of specific heats */
   double gamma_low;      /* linear weight of each linear polynomial */
@@ -572,7 +575,8 @@ int oracle_rhs_2d(const oracle_params *P, int nx, int ny, double dx, double dy, 
         }
       }
       int charwise = P->eq == EQ_EULER && P->char_decomp;
-      for (int sweep = 0; sweep < (charwise ? 2 : 1); ++sweep) {
+      int single = !charwise || P->char_decomp == 2; /* one reconstruction for both directions */
+      for (int sweep = 0; sweep < (single ? 1 : 2); ++sweep) {
         double R[16], L[16];
         if (charwise) {
           double U5[4];
@@ -604,8 +608,8 @@ int oracle_rhs_2d(const oracle_params *P, int nx, int ny, double dx, double dy, 
             wh[k] = tw[k];
           }
         }
-        int do_x = !charwise || sweep == 0;
-        int do_y = !charwise || sweep == 1;
+        int do_x = single || sweep == 0;
+        int do_y = single || sweep == 1;
         if (do_x) {
           for (int e = 0; e < 6; ++e)
             for (int k = 0; k < nc; ++k) out->xe[e][k] = pts[e][k];

@@ -555,6 +555,49 @@ def test_transpose_symmetry_2d_euler():
                                atol=1e-11)
 
 
+def test_projection_modes_agree_with_linear_weights():
+    """With linear weights the reconstruction is linear and commutes with any
+    invertible projection, so component-wise, direction-split
+    characteristic and single-projection characteristic reconstruction give
+    the same right-hand side (to rounding)."""
+    n = 12
+    u, m = W.euler_2d_vortex_quadrant(n, seed=63, q=2)
+    outs = []
+    for mode in (0, 1, 2):
+        P = Problem(2, "euler", (n, n), (0, 10, 0, 10), weights="linear", char_decomp=mode)
+        outs.append(P.rhs(u, m, P.max_wavespeed(u)))
+    for a in outs[1:]:
+        for x, y in zip(a, outs[0]):
+            assert np.abs(x - y).max() <= 1e-11 * np.abs(y).max()
+
+
+def test_single_projection_uses_the_x_eigenvectors():
+    """On data constant in y (periodic) the y-fluxes cancel exactly, so the
+    average and x-moment right-hand sides and v^ come from the x-direction
+    reconstruction alone: the single projection (x-eigenvectors for every
+    output) reproduces the direction-split scheme's F1, F2 and v^ to
+    rounding, while its y-moment terms (built from the x-projection instead
+    of the y-projection) differ."""
+    n = 16
+    u1, m1 = W.euler_1d_shocktube(n, seed=64)
+    u = np.repeat(u1[:, None, :], n, axis=1)
+    u = np.insert(u, 2, 0.3 * u[0], axis=0)  # y-momentum: a uniform v = 0.3
+    u[3] += 0.5 * 0.09 * u[0]  # its kinetic energy
+    m = np.zeros((2, 4, n, n))
+    m[0, [0, 1, 3]] = np.repeat(m1[0][:, None, :], n, axis=1)
+    m[0, 2] = 0.3 * m[0, 0]
+    m[0, 3] += 0.5 * 0.09 * m[0, 0]
+    res = {}
+    for mode in (1, 2):
+        P = Problem(2, "euler", (n, n), (0, 1, 0, 1), char_decomp=mode)
+        res[mode] = P.rhs(u, m, P.max_wavespeed(u))
+    (F1a, Fma, mha), (F1b, Fmb, mhb) = res[1], res[2]
+    assert np.abs(F1b - F1a).max() <= 1e-12 * np.abs(F1a).max()
+    assert np.abs(Fmb[0] - Fma[0]).max() <= 1e-12 * np.abs(Fma[0]).max()
+    assert np.abs(mhb[0] - mha[0]).max() <= 1e-12 * np.abs(mha[0]).max()
+    assert np.abs(Fmb[1] - Fma[1]).max() > 1e-6 * np.abs(Fma[1]).max()
+
+
 def test_2d_reduces_to_1d_for_y_constant_data():
     n = 16
     u1, v1 = W.random_smooth_1d(n, 1, seed=41)
