@@ -9,7 +9,7 @@ moment modification, fluxes, update), replayed from a captured HIP graph.
 
 Reported on the default workload: cell-stage updates per second of the mixed
 form (`value`) and of the plain FP64 form, the same for component-wise
-reconstruction, the mixed-vs-FP64 L1 difference after the timed run next to
+reconstruction and for one x-characteristic reconstruction per cell, the mixed-vs-FP64 L1 difference after the timed run next to
 the FP64 difference between the 1024^2 and 2048^2 solutions at the same time,
 the stage kernel's roofline position, and the CPU oracle on a bounded sample.
 
@@ -390,6 +390,13 @@ def main():
             cw[prec] = {"value": rc["rate"], "ms_per_step": rc["ms_per_step"],
                         "status": rc["status"]}
         line["componentwise"] = cw
+        sp = {}
+        for prec in precs:
+            print(f"[bench] single x-projection {prec}", file=sys.stderr, flush=True)
+            rc = run_case(H, torch, case, prec, steps, args.warmup, False, char_decomp=2)
+            sp[prec] = {"value": rc["rate"], "ms_per_step": rc["ms_per_step"],
+                        "status": rc["status"]}
+        line["single_projection"] = sp
         if "fp64" in results and n % 2 == 0 and "mixed_vs_fp64" in line:
             print("[bench] FP64 mesh difference", file=sys.stderr, flush=True)
             tf = results["fp64"]["t"][0]

@@ -57,6 +57,12 @@ enum { HWENOU_FP64 = 0, HWENOU_MIXED = 1 };
 /* nonlinear weights: scale-invariant (Eq. (2.8)/(2.14)), the scale-dependent
  * original (u_ave = 1, Remark 2.1 of Section 2.1), or linear (w = gamma). */
 enum { HWENOU_W_SCALE_INVARIANT = 0, HWENOU_W_ZQ = 1, HWENOU_W_LINEAR = 2 };
+/* Euler reconstruction variables (Remark 2.1): conserved variables
+ * (component-wise); local characteristic variables in direction-split sweeps
+ * (x-edges, f and v^ from the x-projection, y-edges, g and w^ from the
+ * y-projection; the default); or one reconstruction in x-characteristic
+ * variables for every output (2D; the same as SPLIT in 1D). */
+enum { HWENOU_CHAR_COMPONENT = 0, HWENOU_CHAR_SPLIT = 1, HWENOU_CHAR_SINGLE = 2 };
 /* boundary conditions per side: periodic; transmissive (outflow: ghost cells
  * copy the boundary cell); reflective (Euler only: a solid wall, ghost cells
  * are mirror images with the wall-normal momentum negated and the moments
@@ -71,7 +77,7 @@ typedef struct hwenou_desc {
                        Burgers: f = g = u^2/2; Euler: ideal gas */
   int precision;    /* HWENOU_FP64 or HWENOU_MIXED (FP64 averages, smoothness
                        indicators and weights; FP32 moments, point values, fluxes) */
-  int char_decomp;  /* Euler: 1 = local characteristic variables, 0 = conserved */
+  int char_decomp;  /* Euler: HWENOU_CHAR_* */
   int weights;      /* HWENOU_W_* */
   double adv[2];    /* advection velocity */
   double gas_gamma; /* ratio of specific heats (Euler) */
@@ -96,8 +102,9 @@ typedef struct hwenou_handle hwenou_handle;
  * ordered on it.  The handle owns its scratch: the stage buffers used by
  * hwenou_advance, the stored modified moments of stage 0, per-instance
  * alpha/dt/t/step arrays and the work lists.  Errors: EINVAL (dim, eq,
- * precision or weights out of range; n_inst < 1; nx or ny < 3; overlapping
- * instances; gas_gamma <= 1 for Euler; a reflective side for a scalar law),
+ * precision, weights or char_decomp out of range; n_inst < 1; nx or ny < 3;
+ * overlapping instances; gas_gamma <= 1 for Euler; a reflective side for a
+ * scalar law),
  * EUNSUPPORTED (an instance of more than 2^29 cells: the kernels address an
  * instance with 32-bit byte offsets), ENOMEM, EHIP.  On error *out is NULL. */
 int hwenou_create(const hwenou_desc* desc, int n_inst, const hwenou_inst* inst, void* stream,

@@ -27,6 +27,8 @@ EQ = {"advection": 0, "burgers": 1, "euler": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 WEIGHTS = {"scale_invariant": 0, "zq": 1, "linear": 2}
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+# Euler reconstruction variables: True / 1 = "split" (default), False / 0, 2 = "single"
+CHAR = {"component": 0, "split": 1, "single": 2}
 
 EXPORTS = ["hwenou_create", "hwenou_destroy", "hwenou_strerror", "hwenou_max_wavespeed",
            "hwenou_stage", "hwenou_advance", "hwenou_status", "hwenou_set_launch",
@@ -113,7 +115,7 @@ def make_desc(dim, eq, precision="fp64", char_decomp=True, weights="scale_invari
     d.dim = dim
     d.eq = EQ[eq]
     d.precision = PRECISION[precision]
-    d.char_decomp = int(bool(char_decomp))
+    d.char_decomp = CHAR[char_decomp] if isinstance(char_decomp, str) else int(char_decomp)
     d.weights = WEIGHTS[weights]
     d.adv[0] = float(adv[0])
     d.adv[1] = float(adv[1]) if len(adv) > 1 else 0.0

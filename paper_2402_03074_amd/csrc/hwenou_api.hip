@@ -110,7 +110,7 @@ int build_work(hwenou_handle* h) {
   // default: as many waves per compute unit as can be resident at once
   int wpc = h->waves_per_cu;
   if (wpc <= 0) {
-    const bool chr = h->desc.eq == HWENOU_EQ_EULER && h->desc.char_decomp;
+    const int chr = h->desc.eq == HWENOU_EQ_EULER ? h->desc.char_decomp : 0;
     if (h->dim == 1)
       wpc = 4 * occupancy_stage_1d(h->desc.eq, chr, h->mixed, 256);
     else
@@ -202,7 +202,7 @@ int launch_stage(hwenou_handle* h, int s, const double* dt, const double* alpha,
     if (rc) return rc;
   }
   const SchemeParams P = scheme_params(h->desc);
-  const bool chr = h->desc.eq == HWENOU_EQ_EULER && h->desc.char_decomp;
+  const int chr = h->desc.eq == HWENOU_EQ_EULER ? h->desc.char_decomp : 0;
   hipError_t e;
   auto fill = [&](auto& A, auto* mi, auto* mo, auto* mb) {
     A.P = P;
@@ -293,6 +293,8 @@ int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, voi
   if (d->eq < HWENOU_EQ_ADVECTION || d->eq > HWENOU_EQ_EULER) return HWENOU_EINVAL;
   if (d->precision != HWENOU_FP64 && d->precision != HWENOU_MIXED) return HWENOU_EINVAL;
   if (d->weights < HWENOU_W_SCALE_INVARIANT || d->weights > HWENOU_W_LINEAR) return HWENOU_EINVAL;
+  if (d->char_decomp < HWENOU_CHAR_COMPONENT || d->char_decomp > HWENOU_CHAR_SINGLE)
+    return HWENOU_EINVAL;
   if (!(d->gamma_low > 0.0) || d->gamma_low * (d->dim == 1 ? 2 : 4) >= 1.0) return HWENOU_EINVAL;
   if (!(d->eps >= 0.0)) return HWENOU_EINVAL;
   if (d->eq == HWENOU_EQ_EULER && !(d->gas_gamma > 1.0)) return HWENOU_EINVAL;
@@ -423,7 +425,7 @@ int hwenou_autotune(hwenou_handle* h, const double* ubar, const void* mom, int r
                     int* waves_per_cu, int* rows_per_item) {
   if (!h || !ubar || !mom || reps < 1 || !aligned(ubar, 8) || !aligned(mom, h->mom_elem))
     return HWENOU_EINVAL;
-  const bool chr = h->desc.eq == HWENOU_EQ_EULER && h->desc.char_decomp;
+  const int chr = h->desc.eq == HWENOU_EQ_EULER ? h->desc.char_decomp : 0;
   const int occ = h->dim == 1 ? 4 * occupancy_stage_1d(h->desc.eq, chr, h->mixed, 256)
                               : occupancy_stage_2d(h->desc.eq, chr, h->mixed, 64);
   const int base = occ > 0 ? occ : 4;

@@ -49,15 +49,17 @@ struct StageArgs {
   int stage;            // 0, 1, 2
 };
 
-// kernel launchers (one per translation unit); return hipSuccess or the launch error
-hipError_t launch_stage_1d(int eq, bool char_decomp, bool mixed, const void* args, int blocks,
+// kernel launchers (one per translation unit); return hipSuccess or the launch error.
+// char_mode (Euler): 0 component-wise, 1 direction-split characteristic, 2 single
+// x-projection (the same as 1 in 1D)
+hipError_t launch_stage_1d(int eq, int char_mode, bool mixed, const void* args, int blocks,
                            int threads, hipStream_t s);
-hipError_t launch_stage_2d(int eq, bool char_decomp, bool mixed, const void* args, int blocks,
+hipError_t launch_stage_2d(int eq, int char_mode, bool mixed, const void* args, int blocks,
                            int threads, hipStream_t s);
 
 // resident blocks per compute unit of a stage kernel at `threads` per block
-int occupancy_stage_1d(int eq, bool char_decomp, bool mixed, int threads);
-int occupancy_stage_2d(int eq, bool char_decomp, bool mixed, int threads);
+int occupancy_stage_1d(int eq, int char_mode, bool mixed, int threads);
+int occupancy_stage_2d(int eq, int char_mode, bool mixed, int threads);
 
 // auxiliary kernels
 struct AuxArgs {

@@ -224,7 +224,7 @@ static hipError_t launch(const void* args, int blocks, int threads, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_stage_1d(int eq, bool char_decomp, bool mixed, const void* args, int blocks,
+hipError_t launch_stage_1d(int eq, int char_decomp, bool mixed, const void* args, int blocks,
                            int threads, hipStream_t s) {
   if (mixed) {
     switch (eq) {
@@ -253,7 +253,7 @@ static int occupancy(int threads) {
   return blocks;
 }
 
-int occupancy_stage_1d(int eq, bool char_decomp, bool mixed, int threads) {
+int occupancy_stage_1d(int eq, int char_decomp, bool mixed, int threads) {
   if (mixed) {
     switch (eq) {
       case EQ_ADVECTION: return occupancy<EQ_ADVECTION, false, float, float>(threads);

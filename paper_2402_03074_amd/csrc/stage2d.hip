@@ -247,9 +247,13 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
   back_project<DIR, 3, TR>(C, rcol, Cc, false);
 }
 
-template <int EQ, bool CHAR, class TR, class TM>
+// CHAR (Euler): 0 component-wise; 1 direction-split characteristic sweeps;
+// 2 one reconstruction in x-characteristic variables for every output.
+template <int EQ, int CHAR, class TR, class TM>
 __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 4 : 1;
+  constexpr bool PROJ = EQ == EQ_EULER && CHAR != 0;   // characteristic variables
+  constexpr bool SPLIT = EQ == EQ_EULER && CHAR == 1;  // a second, x-direction sweep
   __shared__ RowBuf<NC, TM> B;
   __shared__ TR c1buf[15][64];  // entropy-field polynomial shared by the two sweeps
   const int lane = threadIdx.x;
@@ -404,12 +408,12 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
       // ---- reconstruction of row j, y-direction ----
       TR Cc[NC][15];
       Prim pr;
-      if constexpr (EQ == EQ_EULER && CHAR) {
+      if constexpr (PROJ) {
         double U5[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
         pr = make_prim(gm1, U5);
-        char_sweep<1, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, false);
+        char_sweep<SPLIT ? 1 : 0, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, false);
       } else {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
@@ -450,7 +454,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
             phys_flux<EQ, NC, 1, TR>(P, in[H], g);
 #pragma unroll
             for (int k = 0; k < NC; ++k) volg[k] += wgt * g[k];
-            if constexpr (!(EQ == EQ_EULER && CHAR)) {
+            if constexpr (!SPLIT) {
               TR f[NC];
               phys_flux<EQ, NC, 0, TR>(P, in[H], f);
 #pragma unroll
@@ -530,7 +534,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 
       if (row_out) {
         // ---- x-direction reconstruction of row j ----
-        if constexpr (EQ == EQ_EULER && CHAR)
+        if constexpr (SPLIT)
           char_sweep<0, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, true);
         double F1x[NC];
         TR F2x[NC], F3x[NC];
@@ -549,7 +553,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
             restrict_eta<TR>(Cc[k], yh, d);
             eval5<TR>(d, xm[k], xp[k], in[0][k], in[1][k], in[2][k]);
           }
-          if constexpr (EQ == EQ_EULER && CHAR) {
+          if constexpr (SPLIT) {
 #pragma unroll
             for (int G = 0; G < 3; ++G) {
               TR f[NC];
@@ -602,59 +606,56 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
   }
 }
 
-template <int EQ, bool CHAR, class TR, class TM>
+template <int EQ, int CHAR, class TR, class TM>
 static hipError_t launch(const void* args, int blocks, int threads, hipStream_t s) {
   const auto& a = *static_cast<const StageArgs<TM>*>(args);
   hipLaunchKernelGGL((stage2d_kernel<EQ, CHAR, TR, TM>), dim3(blocks), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_stage_2d(int eq, bool char_decomp, bool mixed, const void* args, int blocks,
-                           int threads, hipStream_t s) {
-  if (mixed) {
-    switch (eq) {
-      case EQ_ADVECTION: return launch<EQ_ADVECTION, false, float, float>(args, blocks, threads, s);
-      case EQ_BURGERS: return launch<EQ_BURGERS, false, float, float>(args, blocks, threads, s);
-      default:
-        return char_decomp ? launch<EQ_EULER, true, float, float>(args, blocks, threads, s)
-                           : launch<EQ_EULER, false, float, float>(args, blocks, threads, s);
-    }
-  }
+template <class TR>
+static hipError_t launch_t(int eq, int char_mode, const void* args, int blocks, int threads,
+                           hipStream_t s) {
   switch (eq) {
-    case EQ_ADVECTION: return launch<EQ_ADVECTION, false, double, double>(args, blocks, threads, s);
-    case EQ_BURGERS: return launch<EQ_BURGERS, false, double, double>(args, blocks, threads, s);
+    case EQ_ADVECTION: return launch<EQ_ADVECTION, 0, TR, TR>(args, blocks, threads, s);
+    case EQ_BURGERS: return launch<EQ_BURGERS, 0, TR, TR>(args, blocks, threads, s);
     default:
-      return char_decomp ? launch<EQ_EULER, true, double, double>(args, blocks, threads, s)
-                         : launch<EQ_EULER, false, double, double>(args, blocks, threads, s);
+      if (char_mode == 2) return launch<EQ_EULER, 2, TR, TR>(args, blocks, threads, s);
+      return char_mode ? launch<EQ_EULER, 1, TR, TR>(args, blocks, threads, s)
+                       : launch<EQ_EULER, 0, TR, TR>(args, blocks, threads, s);
   }
 }
 
-template <int EQ, bool CHAR, class TR, class TM>
+hipError_t launch_stage_2d(int eq, int char_mode, bool mixed, const void* args, int blocks,
+                           int threads, hipStream_t s) {
+  return mixed ? launch_t<float>(eq, char_mode, args, blocks, threads, s)
+               : launch_t<double>(eq, char_mode, args, blocks, threads, s);
+}
+
+template <int EQ, int CHAR, class TR>
 static int occupancy(int threads) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stage2d_kernel<EQ, CHAR, TR, TM>, threads, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stage2d_kernel<EQ, CHAR, TR, TR>, threads,
+                                                   0) != hipSuccess)
     return 0;
   return blocks;
 }
 
-int occupancy_stage_2d(int eq, bool char_decomp, bool mixed, int threads) {
-  if (mixed) {
-    switch (eq) {
-      case EQ_ADVECTION: return occupancy<EQ_ADVECTION, false, float, float>(threads);
-      case EQ_BURGERS: return occupancy<EQ_BURGERS, false, float, float>(threads);
-      default:
-        return char_decomp ? occupancy<EQ_EULER, true, float, float>(threads)
-                           : occupancy<EQ_EULER, false, float, float>(threads);
-    }
-  }
+template <class TR>
+static int occupancy_t(int eq, int char_mode, int threads) {
   switch (eq) {
-    case EQ_ADVECTION: return occupancy<EQ_ADVECTION, false, double, double>(threads);
-    case EQ_BURGERS: return occupancy<EQ_BURGERS, false, double, double>(threads);
+    case EQ_ADVECTION: return occupancy<EQ_ADVECTION, 0, TR>(threads);
+    case EQ_BURGERS: return occupancy<EQ_BURGERS, 0, TR>(threads);
     default:
-      return char_decomp ? occupancy<EQ_EULER, true, double, double>(threads)
-                         : occupancy<EQ_EULER, false, double, double>(threads);
+      if (char_mode == 2) return occupancy<EQ_EULER, 2, TR>(threads);
+      return char_mode ? occupancy<EQ_EULER, 1, TR>(threads)
+                       : occupancy<EQ_EULER, 0, TR>(threads);
   }
+}
+
+int occupancy_stage_2d(int eq, int char_mode, bool mixed, int threads) {
+  return mixed ? occupancy_t<float>(eq, char_mode, threads)
+               : occupancy_t<double>(eq, char_mode, threads);
 }
 
 }  // namespace hwenou

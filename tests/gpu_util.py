@@ -52,7 +52,7 @@ def solver_for(P, precision="fp64", **kw):
     p = P.params
     weights = {0: "scale_invariant", 1: "zq", 2: "linear"}[p.weights]
     return H.Solver(P.dim, P.eq, [inst], precision=precision, weights=weights,
-                    char_decomp=bool(p.char_decomp), adv=(p.adv_x, p.adv_y),
+                    char_decomp=int(p.char_decomp), adv=(p.adv_x, p.adv_y),
                     gas_gamma=p.gas_gamma, gamma_low=p.gamma_low, eps=p.eps, **kw)
 
 

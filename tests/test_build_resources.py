@@ -32,9 +32,11 @@ def _usage(src):
 
 
 @pytest.mark.skipif(not os.path.exists(B.HIPCC), reason="hipcc not installed")
-@pytest.mark.parametrize("src", ["stage2d.hip", "stage1d.hip"])
-def test_stage_kernels_use_no_scratch(src):
+# scalar laws (2) and Euler component-wise / characteristic, in 2 precisions;
+# 2D adds the single-projection Euler kernels
+@pytest.mark.parametrize("src,count", [("stage2d.hip", 10), ("stage1d.hip", 8)])
+def test_stage_kernels_use_no_scratch(src, count):
     usage = _usage(src)
     kernels = {k: v for k, v in usage.items() if "stage" in k}
-    assert len(kernels) == 8, kernels  # 3 equations x 2 precisions, Euler both forms
+    assert len(kernels) == count, kernels
     assert all(v == 0 for v in kernels.values()), kernels

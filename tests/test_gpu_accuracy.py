@@ -54,10 +54,11 @@ def test_1d_euler_fifth_order_both_precisions():
     assert abs(e[("mixed", 20)] - e[("fp64", 20)]) <= 0.01 * e[("fp64", 20)]
 
 
-def _vortex_l1(n, T, precision):
+def _vortex_l1(n, T, precision, char_decomp=True):
     u0, m0 = W.euler_2d_vortex(n)
     ue, _ = W.euler_2d_vortex(n, t=T)
-    S = H.Solver(2, "euler", [H.make_inst(n, n, (0.0, 10.0, 0.0, 10.0))], precision=precision)
+    S = H.Solver(2, "euler", [H.make_inst(n, n, (0.0, 10.0, 0.0, 10.0))], precision=precision,
+                 char_decomp=char_decomp)
     ug = torch.tensor(u0.reshape(4, -1), device="cuda")
     mg = torch.tensor(m0.reshape(2, 4, -1), device="cuda").to(S.mom_dtype)
     t, s = S.advance(ug, mg, 0.6, T, 10 ** 6)
@@ -78,3 +79,18 @@ def test_2d_vortex_mixed_matches_fp64_l1_error():
     assert abs(e[("mixed", 64)] - e[("fp64", 64)]) <= 0.01 * e[("fp64", 64)]
     assert e[("mixed", 128)] <= e[("fp64", 128)] + 1.5e-7
     assert e[("fp64", 64)] / e[("fp64", 128)] > 8.0  # at least third order in time
+
+
+def test_2d_vortex_projection_modes():
+    """Cost/accuracy of the reconstruction variables on the smooth vortex
+    (FP64): the single x-projection and the component-wise reconstruction
+    keep the error of the direction-split characteristic scheme within a
+    factor 1.5 and converge at least at third order (the time error) between
+    64^2 and 128^2."""
+    print("[gpu] 2D vortex, projection modes", flush=True)
+    e = {(c, n): _vortex_l1(n, 1.0, "fp64", c) for c in (1, 2, 0) for n in (64, 128)}
+    print({k: f"{v:.4e}" for k, v in e.items()}, flush=True)
+    for c in (2, 0):
+        for n in (64, 128):
+            assert e[(c, n)] <= 1.5 * e[(1, n)]
+        assert e[(c, 64)] / e[(c, 128)] > 8.0

@@ -49,6 +49,9 @@ def _cases():
     u, m = W.euler_2d_vortex_quadrant(64, 64, seed=3003, q=2)
     out.append(("euler2d_quad_64_comp",
                 Problem(2, "euler", (64, 64), (0, 10, 0, 10), char_decomp=False), u, m))
+    u, m = W.euler_2d_vortex_quadrant(130, 70, seed=3004, q=2)
+    out.append(("euler2d_quad_130x70_single",
+                Problem(2, "euler", (130, 70), (0, 10, 0, 10), char_decomp=2), u, m))
     return out
 
 
@@ -72,7 +75,7 @@ def test_one_stage_fp64(case):
 
 @pytest.mark.parametrize("case", [c for c in CASES if c[0] in
                                   ("adv1d_sine_200", "euler1d_tube_1000", "burgers2d_70",
-                                   "euler2d_quad_70x64_trans")],
+                                   "euler2d_quad_70x64_trans", "euler2d_quad_130x70_single")],
                          ids=lambda c: c[0])
 def test_100_steps_fp64(case):
     import torch
@@ -108,7 +111,8 @@ def test_advection_to_final_time_matches_oracle():
 
 
 @pytest.mark.parametrize("case", [c for c in CASES if c[0] in
-                                  ("euler1d_tube_1000", "euler2d_quad_130x96", "burgers2d_70")],
+                                  ("euler1d_tube_1000", "euler2d_quad_130x96", "burgers2d_70",
+                                   "euler2d_quad_130x70_single")],
                          ids=lambda c: c[0])
 def test_one_stage_mixed(case):
     name, P, u0, m0 = case
