@@ -131,8 +131,10 @@ int hwenou_max_wavespeed(hwenou_handle* h, const double* ubar, double* alpha_dev
  * stay valid and unchanged until stage 2 has run, except that stage 2 may
  * write its output into it) and stores v^n in the handle.  dt_dev [n_inst]
  * and alpha_dev [n_inst][2] are device arrays.  `in` and `out` must not
- * alias.  Asynchronous.  Errors: EINVAL (s out of range, stage 1/2 before
- * stage 0, misaligned pointer), EHIP. */
+ * alias.  hwenou_advance and hwenou_autotune run stage 0 themselves and clear
+ * the record, so stage 1 or 2 then needs a new stage 0.  Asynchronous.
+ * Errors: EINVAL (s out of range, stage 1/2 before stage 0, misaligned
+ * pointer), EHIP. */
 int hwenou_stage(hwenou_handle* h, int s, const double* dt_dev, const double* alpha_dev,
                  const double* ubar_in, const void* mom_in, double* ubar_out, void* mom_out);
 

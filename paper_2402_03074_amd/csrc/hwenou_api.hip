@@ -483,6 +483,7 @@ int hwenou_autotune(hwenou_handle* h, const double* ubar, const void* mom, int r
   h->waves_per_cu = rc ? save_w : bw;
   h->rows_per_item = rc ? save_r : br;
   h->work_dirty = true;
+  h->u_base = nullptr;  // the timed stage-0 launches overwrote the stored v^n
   if (rc) return rc == HWENOU_EHIP ? hip_fail(hipGetLastError(), "autotune timing") : rc;
   HIPCHK(hipStreamSynchronize(st));
   if (waves_per_cu) *waves_per_cu = bw;
@@ -592,6 +593,7 @@ int hwenou_advance(hwenou_handle* h, double* ubar, void* mom, double cfl, double
   }
   (void)hipGraphExecDestroy(exec);
   (void)hipGraphDestroy(graph);
+  h->u_base = nullptr;  // the steps' stage-0 launches overwrote the stored v^n
   if (e != hipSuccess) return hip_fail(e, "graph replay");
   HIPCHK(hipStreamSynchronize(st));
   std::vector<double> t(h->n_inst);

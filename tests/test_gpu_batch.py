@@ -210,6 +210,16 @@ def test_stage_api_rejects_stage1_before_stage0():
     assert e.value.code == H.HWENOU_EINVAL
     with pytest.raises(H.HwenouError):
         S.stage(0, dt, al, u, m, u, m)  # aliasing in and out
+    # hwenou_advance runs its own stage 0 (replacing the stored v^n) and
+    # clears the record: a stage 1 after it needs a new stage 0
+    u.copy_(torch.tensor([1.0, 0.2, 0.1, 2.5], dtype=torch.float64,
+                         device="cuda")[:, None].expand_as(u))
+    m.zero_()
+    S.stage(0, dt, al, u, m, u2, m2)
+    S.advance(u, m, 0.6, 1e30, 1)
+    with pytest.raises(H.HwenouError) as e:
+        S.stage(1, dt, al, u2, m2, u, m)
+    assert e.value.code == H.HWENOU_EINVAL
     S.close()
 
 
