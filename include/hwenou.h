@@ -141,7 +141,8 @@ int hwenou_stage(hwenou_handle* h, int s, const double* dt_dev, const double* al
 /* Advance every instance in place until t_final or max_steps steps.  Each
  * step takes alpha from the cell averages of U^n, dt = min(CFL dx / alpha,
  * t_final - t) (1D) or CFL / (alpha_1/dx + alpha_2/dy) clipped likewise (2D),
- * and runs the three stages; whole steps are replayed from a captured HIP
+ * or dt = t_final - t when every wave speed of the instance is zero (all
+ * fluxes vanish), and runs the three stages; whole steps are replayed from a captured HIP
  * graph with dt on the device.  Synchronises once at the end (plus one small
  * read-back per 32 steps to stop early).  t_out [n_inst] and steps_out
  * [n_inst] are host arrays (may be NULL).  Errors: EINVAL (cfl <= 0,

@@ -70,17 +70,20 @@ __global__ __launch_bounds__(256) void dt_kernel(const AuxArgs A) {
       A.dt[k] = 0.0;
       continue;
     }
-    double dt;
-    if (A.dim == 1)
-      dt = A.cfl * I.dx / A.alpha[2 * k];
-    else
-      dt = A.cfl / (A.alpha[2 * k] / I.dx + A.alpha[2 * k + 1] / I.dy);
-    if (!(dt > 0.0) || !isfinite(dt)) {  // zero or non-finite wave speed
+    const double ax = A.alpha[2 * k], ay = A.dim == 1 ? 0.0 : A.alpha[2 * k + 1];
+    if (!isfinite(ax) || !isfinite(ay)) {  // non-finite state: stop and report it
       A.done[k] = 1;
       A.dt[k] = 0.0;
-      atomicOr(A.status, 2);
+      atomicOr(A.status, 1);
       continue;
     }
+    double dt;
+    if (ax == 0.0 && ay == 0.0)
+      dt = A.t_final - t;  // zero wave speed: every flux vanishes, the CFL bound is infinite
+    else if (A.dim == 1)
+      dt = A.cfl * I.dx / ax;
+    else
+      dt = A.cfl / (ax / I.dx + ay / I.dy);
     if (t + dt > A.t_final) dt = A.t_final - t;
     A.dt[k] = dt;
   }

@@ -242,3 +242,30 @@ def test_autotuner_keeps_results_bitwise(tmp_path, monkeypatch):
     assert S2.autotune(ug, mg) == (w, r)
     for s_ in (ref, S, S2):
         s_.close()
+
+
+def test_zero_wave_speed_reaches_final_time():
+    """Advection at zero velocity: every flux vanishes and the CFL bound is
+    infinite, so one step covers the whole interval; the averages are
+    unchanged up to the rounding of the Runge-Kutta combinations."""
+    print("[gpu] zero wave speed", flush=True)
+    P = Problem(1, "advection", 64, (0, 2), adv=(0.0,))
+    u0, m0 = W.advection_sine_1d(64)
+    S = solver_for(P)
+    ug, mg = to_gpu(u0), to_gpu(m0)
+    t, st = S.advance(ug, mg, 0.6, 1.5, 100)
+    assert t == [1.5] and st == [1]
+    assert np.abs(ug.cpu().numpy() - u0).max() <= 1e-15 * np.abs(u0).max()
+    S.close()
+
+
+def test_non_finite_state_is_reported():
+    """A NaN in the averages stops the instance with ENONPHYSICAL."""
+    P = Problem(1, "euler", 64, (0, 1), bc="transmissive")
+    u0, m0 = W.euler_1d_shocktube(64, seed=77)
+    u0[0, 10] = np.nan
+    S = solver_for(P)
+    ug, mg = to_gpu(u0), to_gpu(m0)
+    with pytest.raises(H.NonPhysicalState):
+        S.advance(ug, mg, 0.6, 1e30, 3)
+    S.close()
