@@ -83,6 +83,72 @@ def test_batched_2d_equals_single_instances(precision):
         S1.close()
 
 
+@pytest.mark.parametrize("char_decomp", [1, 2])
+def test_batched_2d_mixed_boundaries_equals_single_instances(char_decomp):
+    """One handle holding instances with different boundary sides (walls,
+    outflow, periodic) gives, bitwise, the single-instance results, for the
+    split and the single-projection reconstruction."""
+    print(f"[gpu] batched 2D, mixed boundaries, char_decomp {char_decomp}", flush=True)
+    sides = [70, 40, 96, 33]
+    bcs = [("reflective",) * 4,
+           ("reflective", "transmissive", "periodic", "periodic"),
+           ("periodic", "periodic", "transmissive", "reflective"),
+           ("transmissive",) * 4]
+    insts, us, ms, off = [], [], [], 0
+    for k, (n, bc) in enumerate(zip(sides, bcs)):
+        u1, m1 = W.euler_2d_vortex_quadrant(n, seed=5300 + k, q=2)
+        insts.append(H.make_inst(n, n, (0.0, 10.0, 0.0, 10.0), bc, offset=off))
+        us.append(u1.reshape(4, -1))
+        ms.append(m1.reshape(2, 4, -1))
+        off += n * n
+    u, m = np.concatenate(us, axis=1), np.concatenate(ms, axis=2)
+    S = H.Solver(2, "euler", insts, char_decomp=char_decomp)
+    ug, mg = to_gpu(u), to_gpu(m)
+    t, steps = S.advance(ug, mg, 0.6, 1e30, 5)
+    got_u, got_m = ug.cpu().numpy(), mg.cpu().numpy()
+    S.close()
+    for k, (I, bc) in enumerate(zip(insts, bcs)):
+        a, b = I.offset, I.offset + I.nx * I.ny
+        S1 = H.Solver(2, "euler", [H.make_inst(I.nx, I.ny, (0.0, 10.0, 0.0, 10.0), bc)],
+                      char_decomp=char_decomp)
+        u1, m1 = to_gpu(u[:, a:b]), to_gpu(m[:, :, a:b])
+        t1, s1 = S1.advance(u1, m1, 0.6, 1e30, 5)
+        assert t1[0] == t[k] and s1[0] == steps[k] == 5
+        assert np.array_equal(u1.cpu().numpy(), got_u[:, a:b]), k
+        assert np.array_equal(m1.cpu().numpy(), got_m[:, :, a:b]), k
+        S1.close()
+
+
+def test_batched_1d_walls_equals_single_instances():
+    """1D: a batch of blast-wave-like instances between walls next to outflow
+    instances equals the single-instance runs bitwise."""
+    print("[gpu] batched 1D walls", flush=True)
+    sizes = [300, 77, 1000, 64]
+    bcs = ["reflective", "transmissive", ("reflective", "transmissive"), "reflective"]
+    insts, us, ms, off = [], [], [], 0
+    for k, (n, bc) in enumerate(zip(sizes, bcs)):
+        u1, m1 = W.euler_1d_shocktube(n, 5400 + k)
+        insts.append(H.make_inst(n, 1, (0.0, 1.0), bc, offset=off))
+        us.append(u1)
+        ms.append(m1)
+        off += n
+    u, m = np.concatenate(us, axis=1), np.concatenate(ms, axis=2)
+    S = H.Solver(1, "euler", insts)
+    ug, mg = to_gpu(u), to_gpu(m)
+    t, steps = S.advance(ug, mg, 0.6, 0.02, 10 ** 5)
+    got_u, got_m = ug.cpu().numpy(), mg.cpu().numpy()
+    S.close()
+    for k, (I, bc) in enumerate(zip(insts, bcs)):
+        a, b = I.offset, I.offset + I.nx
+        S1 = H.Solver(1, "euler", [H.make_inst(I.nx, 1, (0.0, 1.0), bc)])
+        u1, m1 = to_gpu(u[:, a:b]), to_gpu(m[:, :, a:b])
+        t1, s1 = S1.advance(u1, m1, 0.6, 0.02, 10 ** 5)
+        assert t1[0] == t[k] and s1[0] == steps[k]
+        assert np.array_equal(u1.cpu().numpy(), got_u[:, a:b]), k
+        assert np.array_equal(m1.cpu().numpy(), got_m[:, :, a:b]), k
+        S1.close()
+
+
 def test_batch_instances_finish_at_their_own_final_time():
     """Instances of different sizes take different time steps; each stops at
     t_final exactly, matching the oracle run of that instance."""
