@@ -680,6 +680,32 @@ def test_2d_orders_short_time():
     assert np.log2(errs[20] / errs[40]) > 4.5
 
 
+@pytest.mark.slow
+def test_2d_accuracy_tables_coarsest_meshes():
+    """The oracle on the coarsest rows of the 2D tables (Examples 3.3, 3.4):
+    2D Burgers on [0, 4]^2 at 40^2 to T = 0.5/pi, and 2D Euler on one period
+    [0, 2]^2 at 40^2 to T = 2, within a factor 1.5 of the printed errors
+    (measured 0.91-1.29)."""
+    tb, te = _table("burgers2d")[40], _table("euler2d")[40]
+    T = 0.5 / np.pi
+    P = Problem(2, "burgers", (40, 40), (0, 4, 0, 4))
+    u0, m0 = W.burgers_2d_initial(40)
+    ue, _ = W.burgers_2d_exact_moments(40, T)
+    dt = 0.6 / (2 * 1.5 / (4 / 40) ** (5 / 3))
+    steps = int(np.ceil(T / dt))
+    u, m, t, s = P.advance(u0, m0, fixed_dt=T / steps, max_steps=steps)
+    e = np.abs(u[0] - ue[0])
+    assert tb[0] / 1.5 < e.max() < 1.5 * tb[0] and tb[1] / 1.5 < e.mean() < 1.5 * tb[1]
+    P = Problem(2, "euler", (40, 40), (0, 2, 0, 2))
+    u0, m0 = W.euler_2d_sine(40, L=2.0)
+    ue, _ = W.euler_2d_sine(40, t=2.0, L=2.0)
+    dt = 0.6 / (2 * (1 + np.sqrt(1.4 / 0.8)) / (2 / 40) ** (5 / 3))
+    steps = int(np.ceil(2.0 / dt))
+    u, m, t, s = P.advance(u0, m0, fixed_dt=2.0 / steps, max_steps=steps)
+    e = np.abs(u[0] - ue[0])
+    assert te[0] / 1.5 < e.max() < 1.5 * te[0] and te[1] / 1.5 < e.mean() < 1.5 * te[1]
+
+
 def test_theorem1_unmodified_scheme_blows_up():
     """Using v instead of v^ in the Runge-Kutta bases (the unmodified SSP-RK3
     of Theorem 1) is unstable even at CFL 0.1; the modified scheme is not."""

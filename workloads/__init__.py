@@ -321,13 +321,15 @@ def burgers_2d_exact_moments(n, t, q=6):
     return cell_moments_2d(f, (0.0, 4.0, 0.0, 4.0), n, n, q)
 
 
-def euler_2d_sine(n, t=0.0, gas_gamma=GAS_GAMMA, q=4):
-    """Example 3.4: rho = 1 + 0.2 sin(pi (x + y - 2t)), u = v = p = 1 on [0, 4]^2."""
+def euler_2d_sine(n, t=0.0, gas_gamma=GAS_GAMMA, q=4, L=4.0):
+    """Example 3.4: rho = 1 + 0.2 sin(pi (x + y - 2t)), u = v = p = 1 on
+    [0, L]^2 (the text's L = 4; the printed errors belong to one period,
+    L = 2, of the same solution)."""
     def f(X, Y):
         rho = 1.0 + 0.2 * np.sin(np.pi * (X + Y - 2.0 * t))
         one = np.ones_like(rho)
         return prim_to_cons(rho, [one, one], one, gas_gamma)
-    return cell_moments_2d(f, (0.0, 4.0, 0.0, 4.0), n, n, q)
+    return cell_moments_2d(f, (0.0, L, 0.0, L), n, n, q)
 
 
 def vortex_factors(X, Y, xc, yc, strength, gas_gamma=GAS_GAMMA):
