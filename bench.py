@@ -35,8 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # FP64 vector peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz;
 # non-packed FP32 runs at the same instruction rate
 VALU_PEAK_TFLOPS = 78.6
-# dt and finish kernels of one step (rocprofv3 kernel trace: ~5 us + ~4 us)
-AUX_US_PER_STEP = 9.0
+# finish kernel of one step, which also sets the next dt (rocprofv3 kernel
+# trace: ~4 us)
+AUX_US_PER_STEP = 4.0
 COMMON_SOURCES = ["paper_2402_03074_amd/csrc/hwenou_device.hpp",
                   "paper_2402_03074_amd/csrc/hwenou_internal.hpp"]
 KERNEL_SOURCES = ["paper_2402_03074_amd/csrc/stage2d.hip"] + COMMON_SOURCES
@@ -194,10 +195,10 @@ def run_case(H, torch, case, precision, steps, warmup, tune, char_decomp=True, l
     ev_ms = e0.elapsed_time(e1)
     assert sg == [steps] * len(case.insts), sg
 
-    # The timed region is graph replays of whole steps: per step one dt and
-    # one finish kernel (single blocks, ~9 us together by the kernel trace)
-    # and three launches of the stage kernel, so the stage kernel's average
-    # launch duration over the timed region is (region / steps - aux) / 3.
+    # The timed region is graph replays of whole steps: per step three
+    # launches of the stage kernel and one finish kernel (a single block,
+    # ~4 us by the kernel trace), so the stage kernel's average launch
+    # duration over the timed region is (region / steps - aux) / 3.
     stage_ms = (ev_ms / steps - AUX_US_PER_STEP * 1e-3) / 3.0
     status = H.hwenou_status(S.h)
     out = ug.cpu().numpy(), mg.double().cpu().numpy()

@@ -142,10 +142,11 @@ int hwenou_stage(hwenou_handle* h, int s, const double* dt_dev, const double* al
  * step takes alpha from the cell averages of U^n, dt = min(CFL dx / alpha,
  * t_final - t) (1D) or CFL / (alpha_1/dx + alpha_2/dy) clipped likewise (2D),
  * or dt = t_final - t when every wave speed of the instance is zero (all
- * fluxes vanish), and runs the three stages; whole steps are replayed from a captured HIP
- * graph with dt on the device.  Synchronises once at the end (plus one small
- * read-back per 32 steps to stop early).  t_out [n_inst] and steps_out
- * [n_inst] are host arrays (may be NULL).  Errors: EINVAL (cfl <= 0,
+ * fluxes vanish), and runs the three stages.  Whole steps (the three stages
+ * and a finish kernel that also sets the next dt) are replayed from a
+ * captured HIP graph, with alpha and dt on the device.  Synchronises once at
+ * the end (plus one small read-back per 32 steps to stop early).  t_out
+ * [n_inst] and steps_out [n_inst] are host arrays (may be NULL).  Errors: EINVAL (cfl <= 0,
  * t_final < 0, max_steps < 0), ENONPHYSICAL (some instance left the
  * physical states; the arrays hold the last step), EHIP. */
 int hwenou_advance(hwenou_handle* h, double* ubar, void* mom, double cfl, double t_final,

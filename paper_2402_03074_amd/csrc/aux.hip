@@ -55,58 +55,66 @@ hipError_t launch_max_wavespeed(const AuxArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Start of a step: time step per instance, completion test, and the reset of
-// the wave-speed accumulator the last stage fills.
+// Time step of instance k for the step that starts at its current t, from
+// its current alpha; marks the instance done when it has reached t_final or
+// max_steps (dt = 0 then).
+__device__ void set_step(const AuxArgs& A, int k) {
+  const InstDev I = A.inst[k];
+  const double t = A.t[k];
+  const bool finished = A.done[k] || A.steps[k] >= A.max_steps ||
+                        t >= A.t_final * (1.0 - 1e-14);
+  if (finished) {
+    A.done[k] = 1;
+    A.dt[k] = 0.0;
+    return;
+  }
+  const double ax = A.alpha[2 * k], ay = A.dim == 1 ? 0.0 : A.alpha[2 * k + 1];
+  if (!isfinite(ax) || !isfinite(ay)) {  // non-finite state: stop and report it
+    A.done[k] = 1;
+    A.dt[k] = 0.0;
+    atomicOr(A.status, 1);
+    return;
+  }
+  double dt;
+  if (ax == 0.0 && ay == 0.0)
+    dt = A.t_final - t;  // zero wave speed: every flux vanishes, the CFL bound is infinite
+  else if (A.dim == 1)
+    dt = A.cfl * I.dx / ax;
+  else
+    dt = A.cfl / (ax / I.dx + ay / I.dy);
+  if (t + dt > A.t_final) dt = A.t_final - t;
+  A.dt[k] = dt;
+}
+
+// Before the first step: its time step, and the reset of the wave-speed
+// accumulator that the last stage of the step fills.
 __global__ __launch_bounds__(256) void dt_kernel(const AuxArgs A) {
   for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) {
-    const InstDev I = A.inst[k];
     A.alpha_next[2 * k] = 0.0;
     A.alpha_next[2 * k + 1] = 0.0;
-    const double t = A.t[k];
-    const bool finished = A.done[k] || A.steps[k] >= A.max_steps ||
-                          t >= A.t_final * (1.0 - 1e-14);
-    if (finished) {
-      A.done[k] = 1;
-      A.dt[k] = 0.0;
-      continue;
-    }
-    const double ax = A.alpha[2 * k], ay = A.dim == 1 ? 0.0 : A.alpha[2 * k + 1];
-    if (!isfinite(ax) || !isfinite(ay)) {  // non-finite state: stop and report it
-      A.done[k] = 1;
-      A.dt[k] = 0.0;
-      atomicOr(A.status, 1);
-      continue;
-    }
-    double dt;
-    if (ax == 0.0 && ay == 0.0)
-      dt = A.t_final - t;  // zero wave speed: every flux vanishes, the CFL bound is infinite
-    else if (A.dim == 1)
-      dt = A.cfl * I.dx / ax;
-    else
-      dt = A.cfl / (ax / I.dx + ay / I.dy);
-    if (t + dt > A.t_final) dt = A.t_final - t;
-    A.dt[k] = dt;
+    set_step(A, k);
   }
 }
 
-// End of a step: advance t and the step count, take the new wave speed, and
-// count the instances still running.
+// End of a step: advance t and the step count, take the new wave speed,
+// reset its accumulator, set the next step's time step, and count the
+// instances still running (read by the host every few steps).
 __global__ __launch_bounds__(256) void finish_kernel(const AuxArgs A) {
   __shared__ int running;
   if (threadIdx.x == 0) running = 0;
   __syncthreads();
   int mine = 0;
   for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) {
-    if (A.done[k]) continue;
-    A.t[k] += A.dt[k];
-    A.steps[k] += 1;
-    A.alpha[2 * k] = A.alpha_next[2 * k];
-    A.alpha[2 * k + 1] = A.alpha_next[2 * k + 1];
-    const bool finished = A.steps[k] >= A.max_steps || A.t[k] >= A.t_final * (1.0 - 1e-14);
-    if (finished)
-      A.done[k] = 1;
-    else
-      mine = 1;
+    if (!A.done[k]) {
+      A.t[k] += A.dt[k];
+      A.steps[k] += 1;
+      A.alpha[2 * k] = A.alpha_next[2 * k];
+      A.alpha[2 * k + 1] = A.alpha_next[2 * k + 1];
+    }
+    A.alpha_next[2 * k] = 0.0;
+    A.alpha_next[2 * k + 1] = 0.0;
+    set_step(A, k);
+    if (!A.done[k]) mine = 1;
   }
   if (mine) atomicOr(&running, 1);
   __syncthreads();

@@ -545,14 +545,16 @@ int hwenou_advance(hwenou_handle* h, double* ubar, void* mom, double cfl, double
   AuxArgs a = aux_args(h, ubar, cfl, t_final, max_steps);
   hipError_t e = launch_max_wavespeed(a, st);
   if (e != hipSuccess) return hip_fail(e, "max_wavespeed launch");
+  // the first step's dt; later ones are set by the finish kernel of the step before
+  e = launch_dt(a, st);
+  if (e != hipSuccess) return hip_fail(e, "dt launch");
 
-  // capture one step
+  // capture one step: three stages and the finish kernel
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   int rc = HWENOU_OK;
   do {
-    if ((e = launch_dt(a, st)) != hipSuccess) { rc = hip_fail(e, "dt launch"); break; }
     rc = launch_stage(h, 0, h->d_dt, h->d_alpha, h->d_done, ubar, mom, h->s1u, h->s1m, nullptr, st);
     if (rc) break;
     h->u_base = ubar;
