@@ -64,7 +64,7 @@ WORKLOADS = {
     "euler2d-batch64": "64 independent 2D Euler vortex+quadrant grids, sides log-uniform "
                        "in [256, 1024], one persistent launch per stage, per-instance dt",
 }
-DEFAULT_STEPS = {"euler2d-2048": 50, "advection1d-200": 1000, "euler1d-65536": 200,
+DEFAULT_STEPS = {"euler2d-2048": 100, "advection1d-200": 1000, "euler1d-65536": 200,
                  "euler1d-batch512": 200, "euler2d-batch64": 50}
 
 
