@@ -111,10 +111,11 @@ int build_work(hwenou_handle* h) {
   int wpc = h->waves_per_cu;
   if (wpc <= 0) {
     const int chr = h->desc.eq == HWENOU_EQ_EULER ? h->desc.char_decomp : 0;
+    const bool si = h->desc.weights == HWENOU_W_SCALE_INVARIANT;
     if (h->dim == 1)
       wpc = 4 * occupancy_stage_1d(h->desc.eq, chr, h->mixed, 256);
     else
-      wpc = occupancy_stage_2d(h->desc.eq, chr, h->mixed, 64);
+      wpc = occupancy_stage_2d(h->desc.eq, chr, h->mixed, si, 64);
     if (wpc <= 0) wpc = 4;
   }
   const long long target_waves = (long long)h->n_cu * wpc;
@@ -188,7 +189,9 @@ SchemeParams scheme_params(const hwenou_desc& d) {
   P.eps = d.eps;
   P.inv_g0_1d = 1.0 / (1.0 - 2.0 * d.gamma_low);
   P.inv_g0_2d = 1.0 / (1.0 - 4.0 * d.gamma_low);
-  P.weights = d.weights;
+  P.ave_mul = d.weights == HWENOU_W_ZQ ? 0.0 : 1.0;
+  P.ave_add = d.weights == HWENOU_W_ZQ ? 1.0 : 0.0;
+  P.nonlin = d.weights == HWENOU_W_LINEAR ? 0.0 : 1.0;
   return P;
 }
 
@@ -203,6 +206,7 @@ int launch_stage(hwenou_handle* h, int s, const double* dt, const double* alpha,
   }
   const SchemeParams P = scheme_params(h->desc);
   const int chr = h->desc.eq == HWENOU_EQ_EULER ? h->desc.char_decomp : 0;
+  const bool si = h->desc.weights == HWENOU_W_SCALE_INVARIANT;
   hipError_t e;
   auto fill = [&](auto& A, auto* mi, auto* mo, auto* mb) {
     A.P = P;
@@ -231,7 +235,7 @@ int launch_stage(hwenou_handle* h, int s, const double* dt, const double* alpha,
     if (h->dim == 1)
       e = launch_stage_1d(h->desc.eq, chr, true, &A, (h->n_waves + 3) / 4, 256, st);
     else
-      e = launch_stage_2d(h->desc.eq, chr, true, &A, h->n_waves, 64, st);
+      e = launch_stage_2d(h->desc.eq, chr, true, si, &A, h->n_waves, 64, st);
   } else {
     StageArgs<double> A;
     fill(A, static_cast<const double*>(m_in), static_cast<double*>(m_out),
@@ -239,7 +243,7 @@ int launch_stage(hwenou_handle* h, int s, const double* dt, const double* alpha,
     if (h->dim == 1)
       e = launch_stage_1d(h->desc.eq, chr, false, &A, (h->n_waves + 3) / 4, 256, st);
     else
-      e = launch_stage_2d(h->desc.eq, chr, false, &A, h->n_waves, 64, st);
+      e = launch_stage_2d(h->desc.eq, chr, false, si, &A, h->n_waves, 64, st);
   }
   if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
   return HWENOU_OK;
@@ -426,8 +430,9 @@ int hwenou_autotune(hwenou_handle* h, const double* ubar, const void* mom, int r
   if (!h || !ubar || !mom || reps < 1 || !aligned(ubar, 8) || !aligned(mom, h->mom_elem))
     return HWENOU_EINVAL;
   const int chr = h->desc.eq == HWENOU_EQ_EULER ? h->desc.char_decomp : 0;
+  const bool si = h->desc.weights == HWENOU_W_SCALE_INVARIANT;
   const int occ = h->dim == 1 ? 4 * occupancy_stage_1d(h->desc.eq, chr, h->mixed, 256)
-                              : occupancy_stage_2d(h->desc.eq, chr, h->mixed, 64);
+                              : occupancy_stage_2d(h->desc.eq, chr, h->mixed, si, 64);
   const int base = occ > 0 ? occ : 4;
   std::vector<int> wpcs;
   for (int f : {1, 2, 4}) {

@@ -24,7 +24,6 @@
 namespace hwenou {
 
 enum : int { EQ_ADVECTION = 0, EQ_BURGERS = 1, EQ_EULER = 2 };
-enum : int { W_SCALE_INVARIANT = 0, W_ZQ = 1, W_LINEAR = 2 };
 enum : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 
 // Gauss points on [-1/2, 1/2]: 3-point Gauss (sqrt(15)/10, weights 5/18, 4/9)
@@ -44,7 +43,11 @@ struct SchemeParams {
   double eps;           // epsilon of the nonlinear weights
   double inv_g0_1d;     // 1 / (1 - 2 gamma_low)
   double inv_g0_2d;     // 1 / (1 - 4 gamma_low)
-  int weights;          // W_*
+  // weight mode as arithmetic factors (no selects in the kernels):
+  // u_ave <- ave_mul u_ave + ave_add: (1, 0) scale-invariant, (0, 1) ZQ;
+  // nonlin = 1 for nonlinear weights, 0 for linear weights (w = gamma)
+  double ave_mul, ave_add;
+  double nonlin;
 };
 
 // Source cell of index i of a grid of n >= 3 cells, -3 <= i <= n + 2:
@@ -76,11 +79,13 @@ __device__ __forceinline__ int wrap_index(int i, int n, int bc_lo, int bc_hi) {
 // coordinate does.  u: averages [NC]; m: moments [dim][NC] (m[0] along x).
 template <int D, int NC, class T, class TM>
 __device__ __forceinline__ void mirror_cell(T (&u)[NC], TM (*m)[NC], int dim) {
-  u[1 + D] = -u[1 + D];
+  if constexpr (NC > 1 + D) {  // Euler only (scalar laws have no walls)
+    u[1 + D] = -u[1 + D];
 #pragma unroll
-  for (int k = 0; k < NC; ++k)
-    if (k != 1 + D) m[D][k] = -m[D][k];
-  if (dim == 2) m[1 - D][1 + D] = -m[1 - D][1 + D];
+    for (int k = 0; k < NC; ++k)
+      if (k != 1 + D) m[D][k] = -m[D][k];
+    if (dim == 2) m[1 - D][1 + D] = -m[1 - D][1 + D];
+  }
 }
 
 // Global memory access through a wave-uniform base pointer (row and
@@ -119,16 +124,18 @@ __device__ __forceinline__ float rcp_nr(float x) {
 //   a   = w0 / g0          (factor of p0)
 //   b_m = w_m - a g_m      (factor of p_m)
 // so that u_i = a p0 + sum_m b_m p_m.  Always evaluated in FP64.
+// SI = true compiles the scale-invariant weights alone (the default mode);
+// SI = false takes the weight mode from P at run time.
 // ---------------------------------------------------------------------------
-template <int NM>
+template <int NM, bool SI = false>
 __device__ __forceinline__ void combine_factors(const SchemeParams& P, const double (&beta)[NM + 1],
                                                 double u_ave, double& a, double (&b)[NM]) {
-  // The weight mode is applied with selects rather than branches so that the
-  // whole reconstruction of a field stays one basic block.
+  // At run time the weight mode enters through exact arithmetic factors
+  // (multiplications by 0 or 1), so that the reconstruction of a field stays
+  // one basic block without selects.
   const double gl = P.gamma_low;
   const double g0 = 1.0 - NM * gl;
-  const bool linear = P.weights == W_LINEAR;
-  u_ave = P.weights == W_ZQ ? 1.0 : u_ave;
+  if constexpr (!SI) u_ave = fma(u_ave, P.ave_mul, P.ave_add);
   double t = 0.0;
 #pragma unroll
   for (int m = 1; m <= NM; ++m) t += fabs(beta[0] - beta[m]);
@@ -145,9 +152,17 @@ __device__ __forceinline__ void combine_factors(const SchemeParams& P, const dou
   const double inv = rcp_nr(sum);
   // a = w0 / g0 with w0 = wt0 / sum
   const double an = (wt[0] * inv) * (NM == 2 ? P.inv_g0_1d : P.inv_g0_2d);
-  a = linear ? 1.0 : an;
+  if constexpr (SI) {
+    a = an;
 #pragma unroll
-  for (int m = 0; m < NM; ++m) b[m] = linear ? 0.0 : wt[m + 1] * inv - an * gl;
+    for (int m = 0; m < NM; ++m) b[m] = wt[m + 1] * inv - an * gl;
+  } else {
+    // linear weights: a = 1, b = 0 exactly
+    a = fma(an, P.nonlin, 1.0 - P.nonlin);
+    const double inv_n = inv * P.nonlin, agl_n = (an * gl) * P.nonlin;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) b[m] = fma(wt[m + 1], inv_n, -agl_n);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -275,7 +290,7 @@ __device__ __forceinline__ double beta0_2d(const double (&c)[15]) {
 // p3 = u5 + dL xi + dT eta, p4 = u5 + dR xi + dT eta.
 // Combined coefficients C from p0 coefficients c, the centre value u5 and
 // the differences; |u| of cells 2, 4, 5, 6, 8 for u_ave.
-template <class TR>
+template <class TR, bool SI>
 __device__ __forceinline__ void hweno_2d(const SchemeParams& P, const double (&c)[15], double u5,
                                          double dL, double dR, double dB, double dT,
                                          double abs_sum5, TR (&C)[15]) {
@@ -283,7 +298,7 @@ __device__ __forceinline__ void hweno_2d(const SchemeParams& P, const double (&c
   double beta[5] = {beta0_2d(c), lL + lB, lR + lB, lL + lT, lR + lT};
   const double ua = abs_sum5 * 0.2;
   double a, b[4];
-  combine_factors<4>(P, beta, ua * ua, a, b);
+  combine_factors<4, SI>(P, beta, ua * ua, a, b);
   C[0] = (TR)(a * c[0] + ((b[0] + b[1]) + (b[2] + b[3])) * u5);
   C[1] = (TR)(a * c[1] + (b[0] + b[2]) * dL + (b[1] + b[3]) * dR);
   C[2] = (TR)(a * c[2] + (b[0] + b[1]) * dB + (b[2] + b[3]) * dT);

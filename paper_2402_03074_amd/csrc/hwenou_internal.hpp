@@ -54,12 +54,13 @@ struct StageArgs {
 // x-projection (the same as 1 in 1D)
 hipError_t launch_stage_1d(int eq, int char_mode, bool mixed, const void* args, int blocks,
                            int threads, hipStream_t s);
-hipError_t launch_stage_2d(int eq, int char_mode, bool mixed, const void* args, int blocks,
-                           int threads, hipStream_t s);
+// scale_invariant: the default weights, compiled into their own 2D kernels
+hipError_t launch_stage_2d(int eq, int char_mode, bool mixed, bool scale_invariant,
+                           const void* args, int blocks, int threads, hipStream_t s);
 
 // resident blocks per compute unit of a stage kernel at `threads` per block
 int occupancy_stage_1d(int eq, int char_mode, bool mixed, int threads);
-int occupancy_stage_2d(int eq, int char_mode, bool mixed, int threads);
+int occupancy_stage_2d(int eq, int char_mode, bool mixed, bool scale_invariant, int threads);
 
 // auxiliary kernels
 struct AuxArgs {

@@ -132,20 +132,20 @@ __device__ __forceinline__ void read_stencil(const RowBuf<NC, TM>& B, int sb, in
 }
 
 // Scalar HWENO reconstruction of one stencil -> combined coefficients
-template <class TR>
+template <class TR, bool SI>
 __device__ __forceinline__ void recon_scalar(const SchemeParams& P, const Sten2& S, TR (&C)[15]) {
   double c[15];
   p0_coeffs_2d(S, c);
   const double u5 = S.u[4];
   const double asum = fabs(S.u[1]) + fabs(S.u[3]) + fabs(u5) + fabs(S.u[5]) + fabs(S.u[7]);
-  hweno_2d<TR>(P, c, u5, u5 - S.u[3], S.u[5] - u5, u5 - S.u[1], S.u[7] - u5, asum, C);
+  hweno_2d<TR, SI>(P, c, u5, u5 - S.u[3], S.u[5] - u5, u5 - S.u[1], S.u[7] - u5, asum, C);
 }
 
 // One characteristic field K of the sweep in direction DIR: project the
 // stencil with row K of L, reconstruct, and return the combined polynomial C
 // together with column K of R.  The shear field (K = 2) has only two non-zero
 // entries in its L row and R column; they are used directly.
-template <int DIR, int K, class TR, class TM>
+template <int DIR, int K, bool SI, class TR, class TM>
 __device__ __forceinline__ void char_field(const SchemeParams& P, const Prim& pr,
                                            const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
                                            TR (&C)[15], double (&rcol)[4]) {
@@ -185,7 +185,7 @@ __device__ __forceinline__ void char_field(const SchemeParams& P, const Prim& pr
       }
     }
   }
-  recon_scalar<TR>(P, W, C);
+  recon_scalar<TR, SI>(P, W, C);
 }
 
 // add R[:, K] (x) C to the conserved combined coefficients
@@ -215,20 +215,20 @@ __device__ __forceinline__ void back_project(const TR (&C)[15], const double (&r
 // (K = 1) has the same left row and right column in both directions, so its
 // polynomial is reconstructed once per cell (by the first sweep) and passed
 // to the second in C1.
-template <int DIR, class TR, class TM>
+template <int DIR, bool SI, class TR, class TM>
 __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr,
                                            const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
                                            TR (&Cc)[4][15], TR (*c1buf)[64], bool have_c1) {
   TR C[15];
   double rcol[4];
-  char_field<DIR, 0, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
+  char_field<DIR, 0, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
   back_project<DIR, 0, TR>(C, rcol, Cc, true);
   {
     double lrow[4], r1[4];
     eig_row<DIR>(pr, 1, lrow, r1);
     TR C1[15];
     if (!have_c1) {
-      char_field<DIR, 1, TR, TM>(P, pr, B, sb, sc, st, l, C1, r1);
+      char_field<DIR, 1, SI, TR, TM>(P, pr, B, sb, sc, st, l, C1, r1);
 #pragma unroll
       for (int n = 0; n < 15; ++n) c1buf[n][l] = C1[n];  // parked in LDS for the other sweep
     } else {
@@ -240,16 +240,17 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
   // scheduling barriers keep the later fields apart (bounds register pressure;
   // without them the compiler spills to scratch)
   __builtin_amdgcn_sched_barrier(0);
-  char_field<DIR, 2, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
+  char_field<DIR, 2, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
   back_project<DIR, 2, TR>(C, rcol, Cc, false);
   __builtin_amdgcn_sched_barrier(0);
-  char_field<DIR, 3, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
+  char_field<DIR, 3, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
   back_project<DIR, 3, TR>(C, rcol, Cc, false);
 }
 
 // CHAR (Euler): 0 component-wise; 1 direction-split characteristic sweeps;
 // 2 one reconstruction in x-characteristic variables for every output.
-template <int EQ, int CHAR, class TR, class TM>
+// SI: scale-invariant weights compiled in (else the mode comes from P).
+template <int EQ, int CHAR, bool SI, class TR, class TM>
 __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 4 : 1;
   constexpr bool PROJ = EQ == EQ_EULER && CHAR != 0;   // characteristic variables
@@ -413,13 +414,13 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 #pragma unroll
         for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
         pr = make_prim(gm1, U5);
-        char_sweep<SPLIT ? 1 : 0, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, false);
+        char_sweep<SPLIT ? 1 : 0, SI, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, false);
       } else {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
           Sten2 S;
           read_stencil<NC, TM>(B, sb, sc, st, lane, k, S);
-          recon_scalar<TR>(P, S, Cc[k]);
+          recon_scalar<TR, SI>(P, S, Cc[k]);
         }
       }
       // y-edges at (xi_G, -+1/2), interior values for g (and f when the
@@ -535,7 +536,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
       if (row_out) {
         // ---- x-direction reconstruction of row j ----
         if constexpr (SPLIT)
-          char_sweep<0, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, true);
+          char_sweep<0, SI, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, true);
         double F1x[NC];
         TR F2x[NC], F3x[NC];
 #pragma unroll
@@ -606,56 +607,62 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
   }
 }
 
-template <int EQ, int CHAR, class TR, class TM>
+template <int EQ, int CHAR, bool SI, class TR, class TM>
 static hipError_t launch(const void* args, int blocks, int threads, hipStream_t s) {
   const auto& a = *static_cast<const StageArgs<TM>*>(args);
-  hipLaunchKernelGGL((stage2d_kernel<EQ, CHAR, TR, TM>), dim3(blocks), dim3(threads), 0, s, a);
+  hipLaunchKernelGGL((stage2d_kernel<EQ, CHAR, SI, TR, TM>), dim3(blocks), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
-template <class TR>
+template <bool SI, class TR>
 static hipError_t launch_t(int eq, int char_mode, const void* args, int blocks, int threads,
                            hipStream_t s) {
   switch (eq) {
-    case EQ_ADVECTION: return launch<EQ_ADVECTION, 0, TR, TR>(args, blocks, threads, s);
-    case EQ_BURGERS: return launch<EQ_BURGERS, 0, TR, TR>(args, blocks, threads, s);
+    case EQ_ADVECTION: return launch<EQ_ADVECTION, 0, SI, TR, TR>(args, blocks, threads, s);
+    case EQ_BURGERS: return launch<EQ_BURGERS, 0, SI, TR, TR>(args, blocks, threads, s);
     default:
-      if (char_mode == 2) return launch<EQ_EULER, 2, TR, TR>(args, blocks, threads, s);
-      return char_mode ? launch<EQ_EULER, 1, TR, TR>(args, blocks, threads, s)
-                       : launch<EQ_EULER, 0, TR, TR>(args, blocks, threads, s);
+      if (char_mode == 2) return launch<EQ_EULER, 2, SI, TR, TR>(args, blocks, threads, s);
+      return char_mode ? launch<EQ_EULER, 1, SI, TR, TR>(args, blocks, threads, s)
+                       : launch<EQ_EULER, 0, SI, TR, TR>(args, blocks, threads, s);
   }
 }
 
-hipError_t launch_stage_2d(int eq, int char_mode, bool mixed, const void* args, int blocks,
-                           int threads, hipStream_t s) {
-  return mixed ? launch_t<float>(eq, char_mode, args, blocks, threads, s)
-               : launch_t<double>(eq, char_mode, args, blocks, threads, s);
+hipError_t launch_stage_2d(int eq, int char_mode, bool mixed, bool scale_invariant,
+                           const void* args, int blocks, int threads, hipStream_t s) {
+  if (scale_invariant)
+    return mixed ? launch_t<true, float>(eq, char_mode, args, blocks, threads, s)
+                 : launch_t<true, double>(eq, char_mode, args, blocks, threads, s);
+  return mixed ? launch_t<false, float>(eq, char_mode, args, blocks, threads, s)
+               : launch_t<false, double>(eq, char_mode, args, blocks, threads, s);
 }
 
-template <int EQ, int CHAR, class TR>
+template <int EQ, int CHAR, bool SI, class TR>
 static int occupancy(int threads) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stage2d_kernel<EQ, CHAR, TR, TR>, threads,
-                                                   0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stage2d_kernel<EQ, CHAR, SI, TR, TR>,
+                                                   threads, 0) != hipSuccess)
     return 0;
   return blocks;
 }
 
-template <class TR>
+template <bool SI, class TR>
 static int occupancy_t(int eq, int char_mode, int threads) {
   switch (eq) {
-    case EQ_ADVECTION: return occupancy<EQ_ADVECTION, 0, TR>(threads);
-    case EQ_BURGERS: return occupancy<EQ_BURGERS, 0, TR>(threads);
+    case EQ_ADVECTION: return occupancy<EQ_ADVECTION, 0, SI, TR>(threads);
+    case EQ_BURGERS: return occupancy<EQ_BURGERS, 0, SI, TR>(threads);
     default:
-      if (char_mode == 2) return occupancy<EQ_EULER, 2, TR>(threads);
-      return char_mode ? occupancy<EQ_EULER, 1, TR>(threads)
-                       : occupancy<EQ_EULER, 0, TR>(threads);
+      if (char_mode == 2) return occupancy<EQ_EULER, 2, SI, TR>(threads);
+      return char_mode ? occupancy<EQ_EULER, 1, SI, TR>(threads)
+                       : occupancy<EQ_EULER, 0, SI, TR>(threads);
   }
 }
 
-int occupancy_stage_2d(int eq, int char_mode, bool mixed, int threads) {
-  return mixed ? occupancy_t<float>(eq, char_mode, threads)
-               : occupancy_t<double>(eq, char_mode, threads);
+int occupancy_stage_2d(int eq, int char_mode, bool mixed, bool scale_invariant, int threads) {
+  if (scale_invariant)
+    return mixed ? occupancy_t<true, float>(eq, char_mode, threads)
+                 : occupancy_t<true, double>(eq, char_mode, threads);
+  return mixed ? occupancy_t<false, float>(eq, char_mode, threads)
+               : occupancy_t<false, double>(eq, char_mode, threads);
 }
 
 }  // namespace hwenou
