@@ -290,10 +290,10 @@ __device__ __forceinline__ double beta0_2d(const double (&c)[15]) {
 // p3 = u5 + dL xi + dT eta, p4 = u5 + dR xi + dT eta.
 // Combined coefficients C from p0 coefficients c, the centre value u5 and
 // the differences; |u| of cells 2, 4, 5, 6, 8 for u_ave.
-template <class TR, bool SI>
+template <class TR, bool SI, bool FOLD = false>
 __device__ __forceinline__ void hweno_2d(const SchemeParams& P, const double (&c)[15], double u5,
                                          double dL, double dR, double dB, double dT,
-                                         double abs_sum5, TR (&C)[15]) {
+                                         double abs_sum5, TR (&C)[15], double* a_out = nullptr) {
   const double lL = dL * dL, lR = dR * dR, lB = dB * dB, lT = dT * dT;
   double beta[5] = {beta0_2d(c), lL + lB, lR + lB, lL + lT, lR + lT};
   const double ua = abs_sum5 * 0.2;
@@ -302,8 +302,16 @@ __device__ __forceinline__ void hweno_2d(const SchemeParams& P, const double (&c
   C[0] = (TR)(a * c[0] + ((b[0] + b[1]) + (b[2] + b[3])) * u5);
   C[1] = (TR)(a * c[1] + (b[0] + b[2]) * dL + (b[1] + b[3]) * dR);
   C[2] = (TR)(a * c[2] + (b[0] + b[1]) * dB + (b[2] + b[3]) * dT);
+  if constexpr (FOLD) {
+    // C[3..14] left as the p0 coefficients; the caller folds `a` into the
+    // factor it multiplies them with
 #pragma unroll
-  for (int n = 3; n < 15; ++n) C[n] = (TR)(a * c[n]);
+    for (int n = 3; n < 15; ++n) C[n] = (TR)c[n];
+    *a_out = a;
+  } else {
+#pragma unroll
+    for (int n = 3; n < 15; ++n) C[n] = (TR)(a * c[n]);
+  }
 }
 
 // moments of the combined polynomial: int C xi, int C eta over the cell

@@ -132,13 +132,15 @@ __device__ __forceinline__ void read_stencil(const RowBuf<NC, TM>& B, int sb, in
 }
 
 // Scalar HWENO reconstruction of one stencil -> combined coefficients
-template <class TR, bool SI>
-__device__ __forceinline__ void recon_scalar(const SchemeParams& P, const Sten2& S, TR (&C)[15]) {
+template <class TR, bool SI, bool FOLD = false>
+__device__ __forceinline__ void recon_scalar(const SchemeParams& P, const Sten2& S, TR (&C)[15],
+                                             double* a_out = nullptr) {
   double c[15];
   p0_coeffs_2d(S, c);
   const double u5 = S.u[4];
   const double asum = fabs(S.u[1]) + fabs(S.u[3]) + fabs(u5) + fabs(S.u[5]) + fabs(S.u[7]);
-  hweno_2d<TR, SI>(P, c, u5, u5 - S.u[3], S.u[5] - u5, u5 - S.u[1], S.u[7] - u5, asum, C);
+  hweno_2d<TR, SI, FOLD>(P, c, u5, u5 - S.u[3], S.u[5] - u5, u5 - S.u[1], S.u[7] - u5, asum, C,
+                         a_out);
 }
 
 // One characteristic field K of the sweep in direction DIR: project the
@@ -148,7 +150,7 @@ __device__ __forceinline__ void recon_scalar(const SchemeParams& P, const Sten2&
 template <int DIR, int K, bool SI, class TR, class TM>
 __device__ __forceinline__ void char_field(const SchemeParams& P, const Prim& pr,
                                            const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
-                                           TR (&C)[15], double (&rcol)[4]) {
+                                           TR (&C)[15], double& a, double (&rcol)[4]) {
   double lrow[4];
   eig_row<DIR>(pr, K, lrow, rcol);
   Sten2 W;
@@ -185,12 +187,14 @@ __device__ __forceinline__ void char_field(const SchemeParams& P, const Prim& pr
       }
     }
   }
-  recon_scalar<TR, SI>(P, W, C);
+  recon_scalar<TR, SI, true>(P, W, C, &a);
 }
 
-// add R[:, K] (x) C to the conserved combined coefficients
+// add R[:, K] (x) C to the conserved combined coefficients, where C[0..2]
+// are combined coefficients and C[3..14] p0 coefficients still to be scaled
+// by the factor a of p0
 template <int DIR, int K, class TR>
-__device__ __forceinline__ void back_project(const TR (&C)[15], const double (&rcol)[4],
+__device__ __forceinline__ void back_project(const TR (&C)[15], const double (&rcol)[4], double a,
                                              TR (&Cc)[4][15], bool first) {
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -199,13 +203,14 @@ __device__ __forceinline__ void back_project(const TR (&C)[15], const double (&r
       constexpr int t = DIR == 0 ? 2 : 1;
       if (m != t && m != 3) continue;
     }
-    const TR r = (TR)rcol[m];
+    const TR r = (TR)rcol[m], ra = (TR)(rcol[m] * a);
 #pragma unroll
     for (int n = 0; n < 15; ++n) {
+      const TR f = n < 3 ? r : ra;
       if (first)
-        Cc[m][n] = (K == 2) ? (TR)0 : r * C[n];
+        Cc[m][n] = (K == 2) ? (TR)0 : f * C[n];
       else
-        Cc[m][n] += r * C[n];
+        Cc[m][n] += f * C[n];
     }
   }
 }
@@ -220,31 +225,35 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
                                            const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
                                            TR (&Cc)[4][15], TR (*c1buf)[64], bool have_c1) {
   TR C[15];
-  double rcol[4];
-  char_field<DIR, 0, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
-  back_project<DIR, 0, TR>(C, rcol, Cc, true);
+  double rcol[4], a;
+  char_field<DIR, 0, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a, rcol);
+  back_project<DIR, 0, TR>(C, rcol, a, Cc, true);
   {
     double lrow[4], r1[4];
     eig_row<DIR>(pr, 1, lrow, r1);
     TR C1[15];
+    double a1;
     if (!have_c1) {
-      char_field<DIR, 1, SI, TR, TM>(P, pr, B, sb, sc, st, l, C1, r1);
+      char_field<DIR, 1, SI, TR, TM>(P, pr, B, sb, sc, st, l, C1, a1, r1);
+      // parked in LDS for the other sweep
 #pragma unroll
-      for (int n = 0; n < 15; ++n) c1buf[n][l] = C1[n];  // parked in LDS for the other sweep
+      for (int n = 0; n < 15; ++n) c1buf[n][l] = C1[n];
+      c1buf[15][l] = (TR)a1;
     } else {
 #pragma unroll
       for (int n = 0; n < 15; ++n) C1[n] = c1buf[n][l];
+      a1 = (double)c1buf[15][l];
     }
-    back_project<DIR, 1, TR>(C1, r1, Cc, false);
+    back_project<DIR, 1, TR>(C1, r1, a1, Cc, false);
   }
   // scheduling barriers keep the later fields apart (bounds register pressure;
   // without them the compiler spills to scratch)
   __builtin_amdgcn_sched_barrier(0);
-  char_field<DIR, 2, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
-  back_project<DIR, 2, TR>(C, rcol, Cc, false);
+  char_field<DIR, 2, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a, rcol);
+  back_project<DIR, 2, TR>(C, rcol, a, Cc, false);
   __builtin_amdgcn_sched_barrier(0);
-  char_field<DIR, 3, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, rcol);
-  back_project<DIR, 3, TR>(C, rcol, Cc, false);
+  char_field<DIR, 3, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a, rcol);
+  back_project<DIR, 3, TR>(C, rcol, a, Cc, false);
 }
 
 // CHAR (Euler): 0 component-wise; 1 direction-split characteristic sweeps;
@@ -256,7 +265,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
   constexpr bool PROJ = EQ == EQ_EULER && CHAR != 0;   // characteristic variables
   constexpr bool SPLIT = EQ == EQ_EULER && CHAR == 1;  // a second, x-direction sweep
   __shared__ RowBuf<NC, TM> B;
-  __shared__ TR c1buf[15][64];  // entropy-field polynomial shared by the two sweeps
+  __shared__ TR c1buf[16][64];  // entropy-field polynomial shared by the two sweeps
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   if (w >= A.n_waves) return;
