@@ -261,9 +261,17 @@ def test_full_batch_1d_sampled_instances():
 
 
 @pytest.mark.parametrize("weights", ["zq", "linear"])
-def test_weight_modes_one_step(weights):
-    u, m = W.euler_2d_vortex_quadrant(70, 64, seed=3100, q=2)
-    P = Problem(2, "euler", (70, 64), (0, 10, 0, 10), weights=weights)
+@pytest.mark.parametrize("dim", [1, 2])
+def test_weight_modes_one_step(weights, dim):
+    """The scale-dependent (ZQ) and linear weights run in kernels that take
+    the mode at run time; the default scale-invariant weights are covered by
+    every other parity test."""
+    if dim == 1:
+        u, m = W.euler_1d_shocktube(1000, seed=3101)
+        P = Problem(1, "euler", 1000, (0, 1), bc="transmissive", weights=weights)
+    else:
+        u, m = W.euler_2d_vortex_quadrant(70, 64, seed=3100, q=2)
+        P = Problem(2, "euler", (70, 64), (0, 10, 0, 10), weights=weights)
     alpha = P.max_wavespeed(u)
     dt = P.dt_from(alpha, 0.4)
     ref = oracle_three_stages(P, u, m, dt, alpha)
@@ -271,5 +279,5 @@ def test_weight_modes_one_step(weights):
     got = gpu_three_stages(S, P, u, m, dt, alpha, inputs=ref[:2])
     for s in range(3):
         eu, em = state_err(P, got[s], ref[s])
-        assert eu <= TOL_STAGE and em <= TOL_STAGE, (weights, s, eu, em)
+        assert eu <= TOL_STAGE and em <= TOL_STAGE, (weights, dim, s, eu, em)
     S.close()
