@@ -102,9 +102,18 @@ __device__ __forceinline__ void store_at(T* base, unsigned byte_off, T v) {
 }
 
 // ---------------------------------------------------------------------------
-// reciprocals: hardware estimate refined by Newton-Raphson steps
-// r <- r + r (1 - x r); two steps in FP64, one in FP32.  Within a few ulp of
-// the correctly rounded quotient for the normal, finite arguments used here.
+// reciprocals: the hardware estimate refined by Newton-Raphson steps
+// r <- r + r (1 - x r).  Measured on gfx950 over 4M arguments in
+// [1e-20, 1e20] against correctly rounded division: the FP64 estimate is
+// within 4.6e-8 (relative), one step within 2.2e-15 (10 ulp), two steps
+// exact; the FP32 estimate is within 1 ulp, one step exact.
+//   rcp_nr(double): two steps (FP64 kernels, and wherever FP64 is kept);
+//   rcp_w<TR>(double): the FP64 quantities of the reconstruction (weights,
+//     primitive variables for the eigenvectors): two steps for TR = double,
+//     one for the mixed form (TR = float), whose results are FP32;
+//   rcp_nr(float): one step (the mixed form's fluxes).  The 1-ulp estimate
+//     alone is not enough there: over the ~3700 steps of the 80-cell 1D
+//     Euler accuracy test its rounding doubles the mixed form's error floor.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double rcp_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
@@ -112,6 +121,15 @@ __device__ __forceinline__ double rcp_nr(double x) {
   r = fma(r, e, r);
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
+}
+template <class TR>
+__device__ __forceinline__ double rcp_w(double x) {
+  if constexpr (sizeof(TR) == 8) {
+    return rcp_nr(x);
+  } else {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+  }
 }
 __device__ __forceinline__ float rcp_nr(float x) {
   float r = __builtin_amdgcn_rcpf(x);
@@ -127,7 +145,7 @@ __device__ __forceinline__ float rcp_nr(float x) {
 // SI = true compiles the scale-invariant weights alone (the default mode);
 // SI = false takes the weight mode from P at run time.
 // ---------------------------------------------------------------------------
-template <int NM, bool SI = false>
+template <int NM, bool SI, class TR>
 __device__ __forceinline__ void combine_factors(const SchemeParams& P, const double (&beta)[NM + 1],
                                                 double u_ave, double& a, double (&b)[NM]) {
   // At run time the weight mode enters through exact arithmetic factors
@@ -142,14 +160,14 @@ __device__ __forceinline__ void combine_factors(const SchemeParams& P, const dou
   t *= (1.0 / NM);
   const double tau = t * t;
   double wt[NM + 1];
-  wt[0] = g0 * (1.0 + tau * rcp_nr(beta[0] * u_ave + P.eps));
+  wt[0] = g0 * (1.0 + tau * rcp_w<TR>(beta[0] * u_ave + P.eps));
   double sum = wt[0];
 #pragma unroll
   for (int m = 1; m <= NM; ++m) {
-    wt[m] = gl * (1.0 + tau * rcp_nr(beta[m] * u_ave + P.eps));
+    wt[m] = gl * (1.0 + tau * rcp_w<TR>(beta[m] * u_ave + P.eps));
     sum += wt[m];
   }
-  const double inv = rcp_nr(sum);
+  const double inv = rcp_w<TR>(sum);
   // a = w0 / g0 with w0 = wt0 / sum
   const double an = (wt[0] * inv) * (NM == 2 ? P.inv_g0_1d : P.inv_g0_2d);
   if constexpr (SI) {
@@ -201,7 +219,7 @@ __device__ __forceinline__ void hweno_1d(const SchemeParams& P, const double (&c
   double beta[3] = {beta0_1d(c), s1 * s1, s2 * s2};
   const double ua = (aum + au0 + aup) * (1.0 / 3.0);
   double a, b[2];
-  combine_factors<2>(P, beta, ua * ua, a, b);
+  combine_factors<2, false, TR>(P, beta, ua * ua, a, b);
   C[0] = (TR)(a * c[0] + (b[0] + b[1]) * u0);
   C[1] = (TR)(a * c[1] + b[0] * s1 + b[1] * s2);
   C[2] = (TR)(a * c[2]);
@@ -298,7 +316,7 @@ __device__ __forceinline__ void hweno_2d(const SchemeParams& P, const double (&c
   double beta[5] = {beta0_2d(c), lL + lB, lR + lB, lL + lT, lR + lT};
   const double ua = abs_sum5 * 0.2;
   double a, b[4];
-  combine_factors<4, SI>(P, beta, ua * ua, a, b);
+  combine_factors<4, SI, TR>(P, beta, ua * ua, a, b);
   C[0] = (TR)(a * c[0] + ((b[0] + b[1]) + (b[2] + b[3])) * u5);
   C[1] = (TR)(a * c[1] + (b[0] + b[2]) * dL + (b[1] + b[3]) * dR);
   C[2] = (TR)(a * c[2] + (b[0] + b[1]) * dB + (b[2] + b[3]) * dT);

@@ -42,18 +42,19 @@ struct Prim {
   double u, v, c, ci, H, b1, b2, q2;
 };
 
+template <class TR>
 __device__ __forceinline__ Prim make_prim(double gm1, const double (&U)[4]) {
   Prim p;
-  const double rinv = rcp_nr(U[0]);
+  const double rinv = rcp_w<TR>(U[0]);
   p.u = U[1] * rinv;
   p.v = U[2] * rinv;
   p.q2 = p.u * p.u + p.v * p.v;
   const double pr = gm1 * (U[3] - 0.5 * U[0] * p.q2);
   const double c2 = (gm1 + 1.0) * pr * rinv;
   p.c = sqrt(c2);
-  p.ci = rcp_nr(p.c);
+  p.ci = rcp_w<TR>(p.c);
   p.H = (U[3] + pr) * rinv;
-  p.b1 = gm1 * rcp_nr(c2);
+  p.b1 = gm1 * rcp_w<TR>(c2);
   p.b2 = 0.5 * p.b1 * p.q2;
   return p;
 }
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
         double U5[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
-        pr = make_prim(gm1, U5);
+        pr = make_prim<TR>(gm1, U5);
         char_sweep<SPLIT ? 1 : 0, SI, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, false);
       } else {
 #pragma unroll
