@@ -145,14 +145,15 @@ __device__ __forceinline__ void recon_scalar(const SchemeParams& P, const Sten2&
 }
 
 // One characteristic field K of the sweep in direction DIR: project the
-// stencil with row K of L, reconstruct, and return the combined polynomial C
-// together with column K of R.  The shear field (K = 2) has only two non-zero
-// entries in its L row and R column; they are used directly.
+// stencil with row K of L and reconstruct.  Returns C (C[0..2] combined
+// coefficients, C[3..14] p0 coefficients) and the factor a of p0.  The shear
+// field (K = 2) has only two non-zero entries in its L row; they are used
+// directly.
 template <int DIR, int K, bool SI, class TR, class TM>
 __device__ __forceinline__ void char_field(const SchemeParams& P, const Prim& pr,
                                            const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
-                                           TR (&C)[15], double& a, double (&rcol)[4]) {
-  double lrow[4];
+                                           TR (&C)[15], double& a) {
+  double lrow[4], rcol[4];
   eig_row<DIR>(pr, K, lrow, rcol);
   Sten2 W;
   if constexpr (K == 2) {
@@ -191,51 +192,54 @@ __device__ __forceinline__ void char_field(const SchemeParams& P, const Prim& pr
   recon_scalar<TR, SI, true>(P, W, C, &a);
 }
 
-// add R[:, K] (x) C to the conserved combined coefficients, where C[0..2]
-// are combined coefficients and C[3..14] p0 coefficients still to be scaled
-// by the factor a of p0
-template <int DIR, int K, class TR>
-__device__ __forceinline__ void back_project(const TR (&C)[15], const double (&rcol)[4], double a,
-                                             TR (&Cc)[4][15], bool first) {
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    if constexpr (K == 2) {
-      // R column of the shear field: 1 at the tangential momentum, u_t at energy
-      constexpr int t = DIR == 0 ? 2 : 1;
-      if (m != t && m != 3) continue;
-    }
-    const TR r = (TR)rcol[m], ra = (TR)(rcol[m] * a);
-#pragma unroll
-    for (int n = 0; n < 15; ++n) {
-      const TR f = n < 3 ? r : ra;
-      if (first)
-        Cc[m][n] = (K == 2) ? (TR)0 : f * C[n];
-      else
-        Cc[m][n] += f * C[n];
-    }
-  }
-}
-
 // Characteristic sweep in direction DIR: combined polynomials of the four
-// fields mapped back to conserved variables, Cc[m][n].  The entropy field
-// (K = 1) has the same left row and right column in both directions, so its
-// polynomial is reconstructed once per cell (by the first sweep) and passed
-// to the second in C1.
+// fields mapped back to conserved variables, Cc[m][n] = sum_K R[m][K] P_K[n].
+// Each field's polynomial P_K arrives as C with C[0..2] combined and C[3..14]
+// still to be scaled by the factor a of its p0.  The right eigenvectors
+//   r0 = (1, un - c, ut, H - un c), r1 = (1, un, ut, q^2/2),
+//   r2 = (0, 0, 1, ut),             r3 = (1, un + c, ut, H + un c)
+// (components: density, normal momentum, tangential momentum, energy) give
+//   Cc_rho = S + P1,          S = P0 + P3,  D = P3 - P0,
+//   Cc_n   = un Cc_rho + c D,
+//   Cc_t   = ut Cc_rho + P2,
+//   Cc_E   = H S + un c D + q^2/2 P1 + ut P2,
+// so the fields are taken in the order 0, 3, 1, 2 and fold into S, D and
+// then into Cc.  The entropy field (K = 1) has the same left row and right
+// column in both directions: its polynomial is reconstructed once per cell
+// (by the first sweep) and passed to the second through LDS.
 template <int DIR, bool SI, class TR, class TM>
 __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr,
                                            const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
                                            TR (&Cc)[4][15], TR (*c1buf)[64], bool have_c1) {
-  TR C[15];
-  double rcol[4], a;
-  char_field<DIR, 0, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a, rcol);
-  back_project<DIR, 0, TR>(C, rcol, a, Cc, true);
+  constexpr int nd = DIR == 0 ? 1 : 2, td = DIR == 0 ? 2 : 1;  // normal, tangential momentum
+  const double un = DIR == 0 ? pr.u : pr.v, ut = DIR == 0 ? pr.v : pr.u;
+  TR C[15], S[15], D[15];
+  double a;
+  char_field<DIR, 0, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a);
   {
-    double lrow[4], r1[4];
-    eig_row<DIR>(pr, 1, lrow, r1);
+    const TR a0 = (TR)a;
+#pragma unroll
+    for (int n = 0; n < 15; ++n) S[n] = n < 3 ? C[n] : a0 * C[n];  // P0
+  }
+  char_field<DIR, 3, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a);
+  {
+    const TR a3 = (TR)a;
+#pragma unroll
+    for (int n = 0; n < 15; ++n) {
+      const TR p0 = S[n];
+      const TR f = n < 3 ? (TR)1 : a3;
+      S[n] = f * C[n] + p0;
+      D[n] = f * C[n] - p0;
+    }
+  }
+  // scheduling barriers keep the later fields apart (bounds register pressure;
+  // without them the compiler spills to scratch)
+  __builtin_amdgcn_sched_barrier(0);
+  {
     TR C1[15];
     double a1;
     if (!have_c1) {
-      char_field<DIR, 1, SI, TR, TM>(P, pr, B, sb, sc, st, l, C1, a1, r1);
+      char_field<DIR, 1, SI, TR, TM>(P, pr, B, sb, sc, st, l, C1, a1);
       // parked in LDS for the other sweep
 #pragma unroll
       for (int n = 0; n < 15; ++n) c1buf[n][l] = C1[n];
@@ -245,16 +249,27 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
       for (int n = 0; n < 15; ++n) C1[n] = c1buf[n][l];
       a1 = (double)c1buf[15][l];
     }
-    back_project<DIR, 1, TR>(C1, r1, a1, Cc, false);
+    const TR tun = (TR)un, tc = (TR)pr.c, tH = (TR)pr.H, tunc = (TR)(un * pr.c);
+    const TR ta1 = (TR)a1, th = (TR)(0.5 * pr.q2), tha1 = (TR)(0.5 * pr.q2 * a1);
+#pragma unroll
+    for (int n = 0; n < 15; ++n) {
+      const TR f1 = n < 3 ? (TR)1 : ta1, fh = n < 3 ? th : tha1;
+      Cc[0][n] = f1 * C1[n] + S[n];
+      Cc[nd][n] = tun * Cc[0][n] + tc * D[n];
+      Cc[3][n] = fh * C1[n] + (tunc * D[n] + tH * S[n]);
+    }
   }
-  // scheduling barriers keep the later fields apart (bounds register pressure;
-  // without them the compiler spills to scratch)
   __builtin_amdgcn_sched_barrier(0);
-  char_field<DIR, 2, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a, rcol);
-  back_project<DIR, 2, TR>(C, rcol, a, Cc, false);
-  __builtin_amdgcn_sched_barrier(0);
-  char_field<DIR, 3, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a, rcol);
-  back_project<DIR, 3, TR>(C, rcol, a, Cc, false);
+  char_field<DIR, 2, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a);
+  {
+    const TR tut = (TR)ut, a2 = (TR)a, uta2 = (TR)(ut * a);
+#pragma unroll
+    for (int n = 0; n < 15; ++n) {
+      const TR f2 = n < 3 ? (TR)1 : a2, fu = n < 3 ? tut : uta2;
+      Cc[td][n] = f2 * C[n] + tut * Cc[0][n];
+      Cc[3][n] += fu * C[n];
+    }
+  }
 }
 
 // CHAR (Euler): 0 component-wise; 1 direction-split characteristic sweeps;
