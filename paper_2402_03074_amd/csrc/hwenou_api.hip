@@ -187,8 +187,6 @@ SchemeParams scheme_params(const hwenou_desc& d) {
   P.gas_gamma = d.gas_gamma;
   P.gamma_low = d.gamma_low;
   P.eps = d.eps;
-  P.inv_g0_1d = 1.0 / (1.0 - 2.0 * d.gamma_low);
-  P.inv_g0_2d = 1.0 / (1.0 - 4.0 * d.gamma_low);
   P.ave_mul = d.weights == HWENOU_W_ZQ ? 0.0 : 1.0;
   P.ave_add = d.weights == HWENOU_W_ZQ ? 1.0 : 0.0;
   P.nonlin = d.weights == HWENOU_W_LINEAR ? 0.0 : 1.0;

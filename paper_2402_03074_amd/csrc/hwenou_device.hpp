@@ -41,8 +41,6 @@ struct SchemeParams {
   double gas_gamma;     // ratio of specific heats
   double gamma_low;     // linear weight of each linear polynomial
   double eps;           // epsilon of the nonlinear weights
-  double inv_g0_1d;     // 1 / (1 - 2 gamma_low)
-  double inv_g0_2d;     // 1 / (1 - 4 gamma_low)
   // weight mode as arithmetic factors (no selects in the kernels):
   // u_ave <- ave_mul u_ave + ave_add: (1, 0) scale-invariant, (0, 1) ZQ;
   // nonlin = 1 for nonlinear weights, 0 for linear weights (w = gamma)
@@ -159,27 +157,26 @@ __device__ __forceinline__ void combine_factors(const SchemeParams& P, const dou
   for (int m = 1; m <= NM; ++m) t += fabs(beta[0] - beta[m]);
   t *= (1.0 / NM);
   const double tau = t * t;
-  double wt[NM + 1];
-  wt[0] = g0 * (1.0 + tau * rcp_w<TR>(beta[0] * u_ave + P.eps));
-  double sum = wt[0];
+  // unnormalised weights gamma_m e_m with e_m = 1 + tau / (beta_m u_ave + eps)
+  double e[NM + 1];
 #pragma unroll
-  for (int m = 1; m <= NM; ++m) {
-    wt[m] = gl * (1.0 + tau * rcp_w<TR>(beta[m] * u_ave + P.eps));
-    sum += wt[m];
-  }
-  const double inv = rcp_w<TR>(sum);
-  // a = w0 / g0 with w0 = wt0 / sum
-  const double an = (wt[0] * inv) * (NM == 2 ? P.inv_g0_1d : P.inv_g0_2d);
+  for (int m = 0; m <= NM; ++m) e[m] = fma(tau, rcp_w<TR>(beta[m] * u_ave + P.eps), 1.0);
+  double el = e[1];
+#pragma unroll
+  for (int m = 2; m <= NM; ++m) el += e[m];
+  const double inv = rcp_w<TR>(fma(g0, e[0], gl * el));
+  // a = w_0 / gamma_0 = e_0 / sum;  b_m = w_m - a gamma_m = gamma_m (e_m - e_0) / sum
+  const double an = e[0] * inv, gi = gl * inv;
   if constexpr (SI) {
     a = an;
 #pragma unroll
-    for (int m = 0; m < NM; ++m) b[m] = wt[m + 1] * inv - an * gl;
+    for (int m = 0; m < NM; ++m) b[m] = gi * (e[m + 1] - e[0]);
   } else {
     // linear weights: a = 1, b = 0 exactly
     a = fma(an, P.nonlin, 1.0 - P.nonlin);
-    const double inv_n = inv * P.nonlin, agl_n = (an * gl) * P.nonlin;
+    const double gi_n = gi * P.nonlin;
 #pragma unroll
-    for (int m = 0; m < NM; ++m) b[m] = fma(wt[m + 1], inv_n, -agl_n);
+    for (int m = 0; m < NM; ++m) b[m] = gi_n * (e[m + 1] - e[0]);
   }
 }
 
@@ -458,15 +455,17 @@ __device__ __forceinline__ void phys_flux(const SchemeParams& P, const T (&U)[NC
   }
 }
 
-// Lax-Friedrichs flux 1/2 [F(u-) + F(u+) - alpha (u+ - u-)]
+// Twice the Lax-Friedrichs flux: F(u-) + F(u+) - alpha (u+ - u-).  The
+// callers fold the factor 1/2 into their quadrature weights (exactly: a
+// power of two).
 template <int EQ, int NC, int DIR, class T>
-__device__ __forceinline__ void lf_flux(const SchemeParams& P, const T (&um)[NC], const T (&up)[NC],
-                                        T alpha, T (&fh)[NC]) {
+__device__ __forceinline__ void lf_flux2(const SchemeParams& P, const T (&um)[NC], const T (&up)[NC],
+                                         T alpha, T (&fh2)[NC]) {
   T fm[NC], fp[NC];
   phys_flux<EQ, NC, DIR, T>(P, um, fm);
   phys_flux<EQ, NC, DIR, T>(P, up, fp);
 #pragma unroll
-  for (int k = 0; k < NC; ++k) fh[k] = (T)0.5 * (fm[k] + fp[k] - alpha * (up[k] - um[k]));
+  for (int k = 0; k < NC; ++k) fh2[k] = fm[k] + fp[k] - alpha * (up[k] - um[k]);
 }
 
 // wave speeds |f'(u)| (x) and |g'(u)| (y) of a cell average, and validity

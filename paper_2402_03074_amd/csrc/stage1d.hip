@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
       um[k] = from_prev(pt[3][k]);
       up[k] = pt[0][k];
     }
-    lf_flux<EQ, NC, 0, TR>(P, um, up, alpha, fl);
+    lf_flux2<EQ, NC, 0, TR>(P, um, up, alpha, fl);  // twice the flux
 #pragma unroll
     for (int k = 0; k < NC; ++k) fr[k] = from_next(fl[k]);
 
@@ -184,8 +184,8 @@ __global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
     if (owner) {
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
-        const double F1 = -((double)fr[k] - (double)fl[k]) * idx;
-        const TR F2 = -(fl[k] + fr[k]) * (TR)(0.5 * idx) + vol[k] * (TR)idx;
+        const double F1 = -((double)fr[k] - (double)fl[k]) * (0.5 * idx);
+        const TR F2 = -(fl[k] + fr[k]) * (TR)(0.25 * idx) + vol[k] * (TR)idx;
         const double ub = A.stage == 0 ? 0.0 : Ub[k];
         const double un = ra * ub + rb * (Uc[k] + dt * F1);
         TR mn;

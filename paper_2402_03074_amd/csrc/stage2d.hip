@@ -392,13 +392,12 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
         if (walls) mirror_row(slot, row);
       }
     };
-    auto slot_of = [](int row) { return ((row % 3) + 3) % 3; };
-
     __syncthreads();  // the previous item's reads of B are complete
-    // prologue: rows r0-2 .. r0 into LDS, r0+1 into registers
-    for (int row = r0 - 2; row <= r0; ++row) {
-      fetch(row);
-      store(slot_of(row), row);
+    // prologue: rows r0-2 .. r0 into ring slots 0..2, r0+1 into registers
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      fetch(r0 - 2 + q);
+      store(q, r0 - 2 + q);
     }
     fetch(r0 + 1);
     __syncthreads();
@@ -410,9 +409,9 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
     double amax_x = 0.0, amax_y = 0.0;
     bool ok = true;
 
+    int sb = 0, sc = 1, st = 2;  // ring slots of rows j-1, j, j+1
     for (int j = r0 - 1; j <= r1; ++j) {
       const bool row_out = j >= r0 && j < r1;
-      const int sb = slot_of(j - 1), sc = slot_of(j), st = slot_of(j + 1);
       const bool fin = j - 1 >= r0 && j - 1 < r1;  // row j-1 is finished in this step
 
       // base (u^n, v^n, w^n) of row j-1: the mixed kernel has the registers to
@@ -491,8 +490,8 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
         if (j >= r0) {
           // u- = row below at eta = +1/2, u+ = this row at eta = -1/2
           TR gb[NC];
-          lf_flux<EQ, NC, 1, TR>(P, yprev[G], ym, a2, gb);
-          const TR wg = (TR)g3w(G);
+          lf_flux2<EQ, NC, 1, TR>(P, yprev[G], ym, a2, gb);  // twice the flux
+          const TR wg = (TR)(0.5 * g3w(G));
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             F1n_s[k] += wg * gb[k];       // sum_G w_G g_{G,j-1/2}
@@ -593,10 +592,10 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
           TR um[NC], fl[NC], fr[NC];
 #pragma unroll
           for (int k = 0; k < NC; ++k) um[k] = from_prev(xp[k]);
-          lf_flux<EQ, NC, 0, TR>(P, um, xm, a1, fl);
+          lf_flux2<EQ, NC, 0, TR>(P, um, xm, a1, fl);  // twice the flux
 #pragma unroll
           for (int k = 0; k < NC; ++k) fr[k] = from_next(fl[k]);
-          const TR wg = (TR)g3w(H);
+          const TR wg = (TR)(0.5 * g3w(H));
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             F1x[k] += (double)wg * ((double)fr[k] - (double)fl[k]);
@@ -617,9 +616,13 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 
       // ---- advance the LDS ring: row j+2 from registers, prefetch j+3 ----
       __syncthreads();
-      if (j + 2 <= r1 + 1) store(slot_of(j + 2), j + 2);
+      if (j + 2 <= r1 + 1) store(sb, j + 2);  // row j-1's slot takes row j+2
       if (j + 3 <= r1 + 1) fetch(j + 3);
       __syncthreads();
+      const int s0 = sb;
+      sb = sc;
+      sc = st;
+      st = s0;
     }
     if (!ok) atomicOr(A.status, 1);
     if (A.alpha_next != nullptr) {
