@@ -15,8 +15,17 @@
 
 namespace hwenou {
 
+// Resident waves per SIMD the compiler must allow: the kernel is latency-
+// bound, and the mixed characteristic Euler kernel fits 4 waves per SIMD (128
+// registers) without spilling; the others keep the compiler's choice.
+template <int EQ, bool CHAR, class TR>
+constexpr int min_waves_1d() {
+  return (EQ == EQ_EULER && CHAR && sizeof(TR) == 4) ? 4 : 1;
+}
+
 template <int EQ, bool CHAR, class TR, class TM>
-__global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
+__global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_kernel(
+    const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 3 : 1;
   const int lane = threadIdx.x & 63;
   const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -99,37 +108,63 @@ __global__ __launch_bounds__(256) void stage1d_kernel(const StageArgs<TM> A) {
     // ---- reconstruction: point values at the 4 Gauss-Lobatto nodes, v^ ----
     TR pt[4][NC], vh[NC];
     if constexpr (EQ == EQ_EULER && CHAR) {
-      double L[3][3], R[3][3];
-      euler_eig<3, 0>(P.gas_gamma - 1.0, Uc, L, R);
+      // Characteristic fields of f' at the cell average: left rows
+      //   l_0 = (b2 + u/c, -(b1 u + 1/c), b1) / 2,  l_1 = (1 - b2, b1 u, -b1),
+      //   l_2 = (b2 - u/c, -(b1 u - 1/c), b1) / 2,
+      // right columns r_0 = (1, u - c, H - u c), r_1 = (1, u, u^2/2),
+      // r_2 = (1, u + c, H + u c), with b1 = (gamma - 1)/c^2, b2 = b1 u^2/2.
+      // The point values and moment P_K of the fields map back as
+      //   rho = S + P_1,  m = u rho + c D,  E = H S + u c D + u^2/2 P_1,
+      // with S = P_0 + P_2 and D = P_2 - P_0 (in FP64), so no 3x3 matrix is
+      // kept and fewer values are live while the fields are reconstructed.
+      const double gm1 = P.gas_gamma - 1.0;
+      const double rinv = rcp_w<TR>(Uc[0]);
+      const double u = Uc[1] * rinv;
+      const double pr = gm1 * (Uc[2] - 0.5 * Uc[1] * u);
+      const double c2 = (gm1 + 1.0) * pr * rinv;
+      const double c = sqrt(c2);
+      const double ci = rcp_w<TR>(c);
+      const double H = (Uc[2] + pr) * rinv;
+      const double b1 = gm1 * rcp_w<TR>(c2);
+      const double b2 = 0.5 * b1 * u * u;
+      // one field: project with row (l0, l1, l2), reconstruct, evaluate
+      auto field = [&](double l0, double l1, double l2, double (&q)[5]) {
+        const double wm = l0 * Um[0] + l1 * Um[1] + l2 * Um[2];
+        const double wc = l0 * Uc[0] + l1 * Uc[1] + l2 * Uc[2];
+        const double wp = l0 * Up[0] + l1 * Up[1] + l2 * Up[2];
+        const double vvm = l0 * Vm[0] + l1 * Vm[1] + l2 * Vm[2];
+        const double vvp = l0 * Vp[0] + l1 * Vp[1] + l2 * Vp[2];
+        double cf[5];
+        p0_coeffs_1d(wm, wc, wp, vvm, vvp, cf);
+        TR C[5], pts[4], qm;
+        hweno_1d<TR>(P, cf, wc, wc - wm, wp - wc, fabs(wm), fabs(wc), fabs(wp), C);
+        eval_1d<TR>(C, pts, qm);
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < 4; ++g) q[g] = (double)pts[g];
+        q[4] = (double)qm;
+      };
+      double S[5], D[5], Q[5];  // q[0..3] point values, q[4] the moment
+      field(0.5 * (b2 + u * ci), -0.5 * (b1 * u + ci), 0.5 * b1, Q);
+      field(0.5 * (b2 - u * ci), -0.5 * (b1 * u - ci), 0.5 * b1, S);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) pt[g][k] = (TR)0;
+      for (int g = 0; g < 5; ++g) {
+        D[g] = S[g] - Q[g];
+        S[g] = S[g] + Q[g];
+      }
+      field(1.0 - b2, b1 * u, -b1, Q);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) vh[k] = (TR)0;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        double wm = 0, wc = 0, wp = 0, vvm = 0, vvp = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          wm += L[ch][k] * Um[k];
-          wc += L[ch][k] * Uc[k];
-          wp += L[ch][k] * Up[k];
-          vvm += L[ch][k] * Vm[k];
-          vvp += L[ch][k] * Vp[k];
-        }
-        double c[5];
-        p0_coeffs_1d(wm, wc, wp, vvm, vvp, c);
-        TR C[5];
-        hweno_1d<TR>(P, c, wc, wc - wm, wp - wc, fabs(wm), fabs(wc), fabs(wp), C);
-        TR q[4], qm;
-        eval_1d<TR>(C, q, qm);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const TR r = (TR)R[k][ch];
-#pragma unroll
-          for (int g = 0; g < 4; ++g) pt[g][k] += r * q[g];
-          vh[k] += r * qm;
+      for (int g = 0; g < 5; ++g) {
+        const double rho = S[g] + Q[g];
+        const TR mom = (TR)(u * rho + c * D[g]);
+        const TR en = (TR)(H * S[g] + (u * c) * D[g] + (0.5 * u * u) * Q[g]);
+        if (g < 4) {
+          pt[g][0] = (TR)rho;
+          pt[g][1] = mom;
+          pt[g][2] = en;
+        } else {
+          vh[0] = (TR)rho;
+          vh[1] = mom;
+          vh[2] = en;
         }
       }
     } else {
