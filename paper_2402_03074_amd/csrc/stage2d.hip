@@ -25,6 +25,8 @@
 // once.  Waves take balanced runs of (strip, rows) from a per-wave work list:
 // one persistent launch covers one large grid or many instances of uneven
 // size.
+#include <algorithm>
+
 #include "hwenou_internal.hpp"
 
 namespace hwenou {
@@ -275,7 +277,9 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
 // CHAR (Euler): 0 component-wise; 1 direction-split characteristic sweeps;
 // 2 one reconstruction in x-characteristic variables for every output.
 // SI: scale-invariant weights compiled in (else the mode comes from P).
-template <int EQ, int CHAR, bool SI, class TR, class TM>
+// ST: the Runge-Kutta stage (0, 1, 2), so that its coefficients and the
+// stage-0-only stores are compiled in.
+template <int EQ, int CHAR, bool SI, int ST, class TR, class TM>
 __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 4 : 1;
   constexpr bool PROJ = EQ == EQ_EULER && CHAR != 0;   // characteristic variables
@@ -286,9 +290,9 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
   const int w = blockIdx.x;
   if (w >= A.n_waves) return;
   const SchemeParams& P = A.P;
-  double ra = 0.0, rb = 1.0;
-  if (A.stage == 1) { ra = 0.75; rb = 0.25; }
-  if (A.stage == 2) { ra = 1.0 / 3.0; rb = 2.0 / 3.0; }
+  // out = ra * base + rb * (in + dt F)
+  constexpr double ra = ST == 0 ? 0.0 : (ST == 1 ? 0.75 : 1.0 / 3.0);
+  constexpr double rb = ST == 0 ? 1.0 : (ST == 1 ? 0.25 : 2.0 / 3.0);
   const long long plane = A.plane;
   const double gm1 = P.gas_gamma - 1.0;
 
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
       double ubase[NC];
       TM vbase[NC], wbase[NC];
       const long long orow = I.offset + (long long)(j - 1) * nx;  // row j-1
-      if (early_base && A.stage != 0 && fin) {
+      if (early_base && ST != 0 && fin) {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
           ubase[k] = load_at(A.u_base + (k * plane + orow), ou);
@@ -518,7 +522,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 
       // ---- row j-1 is complete: Runge-Kutta update and store ----
       if (fin) {
-        if (!early_base && A.stage != 0) {
+        if (!early_base && ST != 0) {
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             ubase[k] = load_at(A.u_base + (k * plane + orow), ou);
@@ -531,10 +535,10 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             const double uin = B.u[sb][k][lane + 1];
-            const double ub = A.stage == 0 ? 0.0 : ubase[k];
+            const double ub = ST == 0 ? 0.0 : ubase[k];
             const double un = ra * ub + rb * (uin + dt * F1p[k]);
             TR vn, wn;
-            if (A.stage == 0) {
+            if (ST == 0) {
               store_at(A.m_base + (k * plane + orow), om, (TM)vhp[k]);
               store_at(A.m_base + ((NC + k) * plane + orow), om, (TM)whp[k]);
               vn = vhp[k] + (TR)dt * F2p[k];
@@ -638,7 +642,19 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 template <int EQ, int CHAR, bool SI, class TR, class TM>
 static hipError_t launch(const void* args, int blocks, int threads, hipStream_t s) {
   const auto& a = *static_cast<const StageArgs<TM>*>(args);
-  hipLaunchKernelGGL((stage2d_kernel<EQ, CHAR, SI, TR, TM>), dim3(blocks), dim3(threads), 0, s, a);
+  switch (a.stage) {
+    case 0:
+      hipLaunchKernelGGL((stage2d_kernel<EQ, CHAR, SI, 0, TR, TM>), dim3(blocks), dim3(threads), 0,
+                         s, a);
+      break;
+    case 1:
+      hipLaunchKernelGGL((stage2d_kernel<EQ, CHAR, SI, 1, TR, TM>), dim3(blocks), dim3(threads), 0,
+                         s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((stage2d_kernel<EQ, CHAR, SI, 2, TR, TM>), dim3(blocks), dim3(threads), 0,
+                         s, a);
+  }
   return hipGetLastError();
 }
 
@@ -664,13 +680,21 @@ hipError_t launch_stage_2d(int eq, int char_mode, bool mixed, bool scale_invaria
                : launch_t<false, double>(eq, char_mode, args, blocks, threads, s);
 }
 
-template <int EQ, int CHAR, bool SI, class TR>
-static int occupancy(int threads) {
+template <int EQ, int CHAR, bool SI, int ST, class TR>
+static int occupancy_st(int threads) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stage2d_kernel<EQ, CHAR, SI, TR, TR>,
-                                                   threads, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &blocks, stage2d_kernel<EQ, CHAR, SI, ST, TR, TR>, threads, 0) != hipSuccess)
     return 0;
   return blocks;
+}
+
+// resident blocks per CU common to the three stage kernels
+template <int EQ, int CHAR, bool SI, class TR>
+static int occupancy(int threads) {
+  return std::min(occupancy_st<EQ, CHAR, SI, 0, TR>(threads),
+                  std::min(occupancy_st<EQ, CHAR, SI, 1, TR>(threads),
+                           occupancy_st<EQ, CHAR, SI, 2, TR>(threads)));
 }
 
 template <bool SI, class TR>
