@@ -11,6 +11,8 @@
 // the lane on its left, which keeps the update conservative to round-off.
 // Waves take contiguous runs of tiles from a per-wave work list (a persistent
 // launch), so one launch advances any number of instances of uneven size.
+#include <algorithm>
+
 #include "hwenou_internal.hpp"
 
 namespace hwenou {
@@ -23,7 +25,8 @@ constexpr int min_waves_1d() {
   return (EQ == EQ_EULER && CHAR && sizeof(TR) == 4) ? 4 : 1;
 }
 
-template <int EQ, bool CHAR, class TR, class TM>
+// ST: the Runge-Kutta stage (0, 1, 2), compiled in like the coefficients.
+template <int EQ, bool CHAR, int ST, class TR, class TM>
 __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_kernel(
     const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 3 : 1;
@@ -31,9 +34,9 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
   const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= A.n_waves) return;
   const SchemeParams& P = A.P;
-  double ra = 0.0, rb = 1.0;  // RK combination out = ra * base + rb * (in + dt F)
-  if (A.stage == 1) { ra = 0.75; rb = 0.25; }
-  if (A.stage == 2) { ra = 1.0 / 3.0; rb = 2.0 / 3.0; }
+  // Runge-Kutta combination out = ra * base + rb * (in + dt F)
+  constexpr double ra = ST == 0 ? 0.0 : (ST == 1 ? 0.75 : 1.0 / 3.0);
+  constexpr double rb = ST == 0 ? 1.0 : (ST == 1 ? 0.25 : 2.0 / 3.0);
   const long long plane = A.plane;
 
   for (int it = A.work_ptr[w]; it < A.work_ptr[w + 1]; ++it) {
@@ -65,7 +68,7 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
     for (int k = 0; k < NC; ++k) {
       Uc[k] = u[k * plane + ic];
       Vc[k] = m[k * plane + ic];
-      if (A.stage != 0 && owner) {
+      if (ST != 0 && owner) {
         Ub[k] = A.u_base[k * plane + o];
         Mb[k] = A.m_base[k * plane + o];
       }
@@ -221,10 +224,10 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
       for (int k = 0; k < NC; ++k) {
         const double F1 = -((double)fr[k] - (double)fl[k]) * (0.5 * idx);
         const TR F2 = -(fl[k] + fr[k]) * (TR)(0.25 * idx) + vol[k] * (TR)idx;
-        const double ub = A.stage == 0 ? 0.0 : Ub[k];
+        const double ub = ST == 0 ? 0.0 : Ub[k];
         const double un = ra * ub + rb * (Uc[k] + dt * F1);
         TR mn;
-        if (A.stage == 0) {
+        if (ST == 0) {
           A.m_base[k * plane + o] = (TM)vh[k];
           mn = vh[k] + (TR)dt * F2;
         } else {
@@ -255,7 +258,19 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
 template <int EQ, bool CHAR, class TR, class TM>
 static hipError_t launch(const void* args, int blocks, int threads, hipStream_t s) {
   const auto& a = *static_cast<const StageArgs<TM>*>(args);
-  hipLaunchKernelGGL((stage1d_kernel<EQ, CHAR, TR, TM>), dim3(blocks), dim3(threads), 0, s, a);
+  switch (a.stage) {
+    case 0:
+      hipLaunchKernelGGL((stage1d_kernel<EQ, CHAR, 0, TR, TM>), dim3(blocks), dim3(threads), 0, s,
+                         a);
+      break;
+    case 1:
+      hipLaunchKernelGGL((stage1d_kernel<EQ, CHAR, 1, TR, TM>), dim3(blocks), dim3(threads), 0, s,
+                         a);
+      break;
+    default:
+      hipLaunchKernelGGL((stage1d_kernel<EQ, CHAR, 2, TR, TM>), dim3(blocks), dim3(threads), 0, s,
+                         a);
+  }
   return hipGetLastError();
 }
 
@@ -279,13 +294,21 @@ hipError_t launch_stage_1d(int eq, int char_decomp, bool mixed, const void* args
   }
 }
 
-template <int EQ, bool CHAR, class TR, class TM>
-static int occupancy(int threads) {
+template <int EQ, bool CHAR, int ST, class TR, class TM>
+static int occupancy_st(int threads) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stage1d_kernel<EQ, CHAR, TR, TM>, threads, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stage1d_kernel<EQ, CHAR, ST, TR, TM>,
+                                                   threads, 0) != hipSuccess)
     return 0;
   return blocks;
+}
+
+// resident blocks per CU common to the three stage kernels
+template <int EQ, bool CHAR, class TR, class TM>
+static int occupancy(int threads) {
+  return std::min(occupancy_st<EQ, CHAR, 0, TR, TM>(threads),
+                  std::min(occupancy_st<EQ, CHAR, 1, TR, TM>(threads),
+                           occupancy_st<EQ, CHAR, 2, TR, TM>(threads)));
 }
 
 int occupancy_stage_1d(int eq, int char_decomp, bool mixed, int threads) {
