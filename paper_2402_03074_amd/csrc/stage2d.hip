@@ -418,14 +418,11 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
       const bool row_out = j >= r0 && j < r1;
       const bool fin = j - 1 >= r0 && j - 1 < r1;  // row j-1 is finished in this step
 
-      // base (u^n, v^n, w^n) of row j-1: the mixed kernel has the registers to
-      // load it now and use it after the y-sweep; the FP64 kernel loads it
-      // when the row is finished
-      constexpr bool early_base = sizeof(TR) == 4;
+      // base (u^n, v^n, w^n) of row j-1, loaded now and used after the y-sweep
       double ubase[NC];
       TM vbase[NC], wbase[NC];
       const long long orow = I.offset + (long long)(j - 1) * nx;  // row j-1
-      if (early_base && ST != 0 && fin) {
+      if (ST != 0 && fin) {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
           ubase[k] = load_at(A.u_base + (k * plane + orow), ou);
@@ -522,14 +519,6 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
 
       // ---- row j-1 is complete: Runge-Kutta update and store ----
       if (fin) {
-        if (!early_base && ST != 0) {
-#pragma unroll
-          for (int k = 0; k < NC; ++k) {
-            ubase[k] = load_at(A.u_base + (k * plane + orow), ou);
-            vbase[k] = load_at(A.m_base + (k * plane + orow), om);
-            wbase[k] = load_at(A.m_base + ((NC + k) * plane + orow), om);
-          }
-        }
         if (col_owner) {
           double Uo[NC];
 #pragma unroll
