@@ -543,10 +543,14 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
             store_at(A.m_out + ((NC + k) * plane + orow), om, (TM)wn);
             Uo[k] = un;
           }
-          double sx, sy;
-          ok = wave_speeds<EQ, NC>(P, Uo, sx, sy) && ok;
-          amax_x = fmax(amax_x, sx);
-          amax_y = fmax(amax_y, sy);
+          if constexpr (ST == 2) {  // the wave speeds feed the next step's alpha
+            double sx, sy;
+            ok = wave_speeds<EQ, NC>(P, Uo, sx, sy) && ok;
+            amax_x = fmax(amax_x, sx);
+            amax_y = fmax(amax_y, sy);
+          } else {
+            ok = physical_state<EQ, NC>(Uo) && ok;
+          }
         }
       }
 
@@ -618,7 +622,7 @@ __global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const Stag
       st = s0;
     }
     if (!ok) atomicOr(A.status, 1);
-    if (A.alpha_next != nullptr) {
+    if (ST == 2 && A.alpha_next != nullptr) {
       const double mx = wave_max(amax_x), my = wave_max(amax_y);
       if (lane == 0) {
         atomic_max_nonneg(&A.alpha_next[2 * wk.inst], mx);
