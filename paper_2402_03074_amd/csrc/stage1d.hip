@@ -242,13 +242,13 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
     double sx = 0.0, sy = 0.0;
     bool ok = true;
     if (owner) {
-      if (A.alpha_next != nullptr)  // the wave speeds feed the next step's alpha
+      if (ST == 2 && A.alpha_next != nullptr)  // the wave speeds feed the next step's alpha
         ok = wave_speeds<EQ, NC>(P, Uo, sx, sy);
       else
         ok = physical_state<EQ, NC>(Uo);
     }
     if (!ok) atomicOr(A.status, 1);
-    if (A.alpha_next != nullptr) {
+    if (ST == 2 && A.alpha_next != nullptr) {
       const double mx = wave_max(owner ? sx : 0.0);
       if (lane == 0) atomic_max_nonneg(&A.alpha_next[2 * wk.inst], mx);
     }
