@@ -281,3 +281,41 @@ def test_weight_modes_one_step(weights, dim):
         eu, em = state_err(P, got[s], ref[s])
         assert eu <= TOL_STAGE and em <= TOL_STAGE, (weights, dim, s, eu, em)
     S.close()
+
+
+def _degenerate_cases():
+    """Grids at and around the kernels' tile edges: the smallest grid the
+    method allows (3 cells a side, where the stencils of a periodic grid wrap
+    onto themselves), one 62-column strip or 62-cell tile exactly, one more,
+    and a grid of 64; each with periodic, outflow and wall sides."""
+    out = []
+    for nx, ny in ((3, 3), (3, 5), (62, 3), (63, 4), (64, 7)):
+        u, m = W.euler_2d_vortex_quadrant(nx, ny, seed=5000 + nx + 100 * ny, q=2)
+        for bc in ("periodic", "transmissive", "reflective"):
+            out.append((f"2d_{nx}x{ny}_{bc}",
+                        Problem(2, "euler", (nx, ny), (0, 10, 0, 10), bc=bc), u, m))
+    for n in (3, 4, 61, 62, 63, 64, 125):
+        u, m = W.random_smooth_1d(n, 3, seed=5100 + n, positive_euler=True)
+        for bc in ("periodic", "transmissive", "reflective"):
+            out.append((f"1d_{n}_{bc}", Problem(1, "euler", n, (0, 1), bc=bc), u, m))
+    return out
+
+
+DEGENERATE = _degenerate_cases()
+
+
+@pytest.mark.parametrize("case", DEGENERATE, ids=[c[0] for c in DEGENERATE])
+def test_degenerate_sizes_one_step(case):
+    """One Runge-Kutta step (the three stages) on the smallest and
+    tile-edge grid sizes, FP64, against the oracle at the one-stage bar."""
+    name, P, u, m = case
+    print(f"[gpu] degenerate size {name}", flush=True)
+    alpha = P.max_wavespeed(u)
+    dt = P.dt_from(alpha, 0.5)
+    ref = oracle_three_stages(P, u, m, dt, alpha)
+    S = solver_for(P)
+    got = gpu_three_stages(S, P, u, m, dt, alpha, inputs=ref[:2])
+    for s in range(3):
+        eu, em = state_err(P, got[s], ref[s], floor=1e-3)
+        assert eu <= TOL_STAGE and em <= TOL_STAGE, (name, s, eu, em)
+    S.close()
