@@ -32,9 +32,6 @@
 namespace hwenou {
 
 constexpr int kCols = 66;  // LDS columns: strip*62 - 2 .. strip*62 + 63
-#ifndef HWENOU_2D_WAVES
-#define HWENOU_2D_WAVES 1
-#endif
 
 __device__ __forceinline__ double g3w(int g) { return g == 1 ? G3W1 : G3W0; }
 __device__ __forceinline__ double g3x(int g) { return g == 0 ? -G3S : (g == 1 ? 0.0 : G3S); }
@@ -279,8 +276,10 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
 // SI: scale-invariant weights compiled in (else the mode comes from P).
 // ST: the Runge-Kutta stage (0, 1, 2), so that its coefficients and the
 // stage-0-only stores are compiled in.
+// One wave per block and one resident wave per SIMD (the row state needs
+// 256 VGPRs plus 85-252 AGPRs).
 template <int EQ, int CHAR, bool SI, int ST, class TR, class TM>
-__global__ __launch_bounds__(64, HWENOU_2D_WAVES) void stage2d_kernel(const StageArgs<TM> A) {
+__global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 4 : 1;
   constexpr bool PROJ = EQ == EQ_EULER && CHAR != 0;   // characteristic variables
   constexpr bool SPLIT = EQ == EQ_EULER && CHAR == 1;  // a second, x-direction sweep
