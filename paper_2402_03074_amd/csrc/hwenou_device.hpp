@@ -129,6 +129,19 @@ __device__ __forceinline__ double rcp_w(double x) {
     return fma(r, fma(-x, r, 1.0), r);
   }
 }
+// 1/sqrt(x) for the sound speed of the eigenvectors: the hardware estimate
+// refined by Newton-Raphson steps y <- y (3/2 - x y^2 / 2), as many as rcp_w
+// takes (two for TR = double, one for the mixed form).
+template <class TR>
+__device__ __forceinline__ double rsq_w(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < (sizeof(TR) == 8 ? 2 : 1); ++k) {
+    const double g = x * y, h = 0.5 * y;
+    y = fma(y, fma(-g, h, 0.5), y);
+  }
+  return y;
+}
 __device__ __forceinline__ float rcp_nr(float x) {
   float r = __builtin_amdgcn_rcpf(x);
   const float e = fmaf(-x, r, 1.0f);
@@ -157,10 +170,32 @@ __device__ __forceinline__ void combine_factors(const SchemeParams& P, const dou
   for (int m = 1; m <= NM; ++m) t += fabs(beta[0] - beta[m]);
   t *= (1.0 / NM);
   const double tau = t * t;
-  // unnormalised weights gamma_m e_m with e_m = 1 + tau / (beta_m u_ave + eps)
-  double e[NM + 1];
+  // unnormalised weights gamma_m e_m with e_m = 1 + tau / d_m and
+  // d_m = beta_m u_ave + eps, all scaled by D = prod_k d_k so that one
+  // reciprocal serves every weight: D e_m = D + tau P_m, with P_m the product
+  // of the d_k other than d_m (prefix times suffix products).  The weights are
+  // ratios of these, so the scale cancels exactly.  d_m and tau scale like
+  // the fourth power of the reconstructed variable, so tau P_m like its
+  // (4 NM + 4)th: the products stay finite for variables below ~1e15 in
+  // magnitude (NM = 4; ~1e25 for NM = 2), and eps keeps them from
+  // underflowing.  Beyond that range the weights come out non-finite (the
+  // per-field reciprocals of the plain form reach ~1e77).
+  double d[NM + 1];
 #pragma unroll
-  for (int m = 0; m <= NM; ++m) e[m] = fma(tau, rcp_w<TR>(beta[m] * u_ave + P.eps), 1.0);
+  for (int m = 0; m <= NM; ++m) d[m] = fma(beta[m], u_ave, P.eps);
+  double pre[NM + 1], suf[NM + 1];  // pre[m] = d_0 .. d_{m-1}, suf[m] = d_m .. d_NM
+  pre[1] = d[0];
+#pragma unroll
+  for (int m = 2; m <= NM; ++m) pre[m] = pre[m - 1] * d[m - 1];
+  suf[NM] = d[NM];
+#pragma unroll
+  for (int m = NM - 1; m >= 1; --m) suf[m] = d[m] * suf[m + 1];
+  const double D = d[0] * suf[1];
+  double e[NM + 1];
+  e[0] = fma(tau, suf[1], D);
+#pragma unroll
+  for (int m = 1; m < NM; ++m) e[m] = fma(tau, pre[m] * suf[m + 1], D);
+  e[NM] = fma(tau, pre[NM], D);
   double el = e[1];
 #pragma unroll
   for (int m = 2; m <= NM; ++m) el += e[m];
@@ -373,55 +408,8 @@ __device__ __forceinline__ void eval5(const TR (&d)[5], TR& em, TR& ep, TR& gm, 
 }
 
 // ---------------------------------------------------------------------------
-// Euler: primitive quantities and eigenvectors (ideal gas)
+// Euler: physical fluxes (ideal gas)
 // ---------------------------------------------------------------------------
-// Left eigenvectors L (rows) and right eigenvectors R (columns) of the flux
-// Jacobian in direction DIR at the conserved state U.  NC = 3 (1D) or 4 (2D).
-// 1D right eigenvectors: (1, u-c, H-uc), (1, u, u^2/2), (1, u+c, H+uc).
-// 2D, x: (1, u-c, v, H-uc), (1, u, v, q^2/2), (0, 0, 1, v), (1, u+c, v, H+uc);
-// 2D, y: (1, u, v-c, H-vc), (1, u, v, q^2/2), (0, 1, 0, u), (1, u, v+c, H+vc).
-template <int NC, int DIR>
-__device__ __forceinline__ void euler_eig(double gm1, const double (&U)[NC], double (&L)[NC][NC],
-                                          double (&R)[NC][NC]) {
-  const double rinv = 1.0 / U[0];
-  const double u = U[1] * rinv;
-  const double v = NC == 4 ? U[2] * rinv : 0.0;
-  const double q2 = u * u + v * v;
-  const double p = gm1 * (U[NC - 1] - 0.5 * U[0] * q2);
-  const double c2 = (gm1 + 1.0) * p * rinv;
-  const double c = sqrt(c2);
-  const double ci = 1.0 / c;
-  const double H = (U[NC - 1] + p) * rinv;
-  const double b1 = gm1 / c2;
-  const double b2 = 0.5 * b1 * q2;
-  if constexpr (NC == 3) {
-    L[0][0] = 0.5 * (b2 + u * ci); L[0][1] = -0.5 * (b1 * u + ci); L[0][2] = 0.5 * b1;
-    L[1][0] = 1.0 - b2;            L[1][1] = b1 * u;               L[1][2] = -b1;
-    L[2][0] = 0.5 * (b2 - u * ci); L[2][1] = -0.5 * (b1 * u - ci); L[2][2] = 0.5 * b1;
-    R[0][0] = 1.0;        R[0][1] = 1.0;          R[0][2] = 1.0;
-    R[1][0] = u - c;      R[1][1] = u;            R[1][2] = u + c;
-    R[2][0] = H - u * c;  R[2][1] = 0.5 * u * u;  R[2][2] = H + u * c;
-  } else if constexpr (DIR == 0) {
-    L[0][0] = 0.5 * (b2 + u * ci); L[0][1] = -0.5 * (b1 * u + ci); L[0][2] = -0.5 * b1 * v; L[0][3] = 0.5 * b1;
-    L[1][0] = 1.0 - b2;            L[1][1] = b1 * u;               L[1][2] = b1 * v;        L[1][3] = -b1;
-    L[2][0] = -v;                  L[2][1] = 0.0;                  L[2][2] = 1.0;           L[2][3] = 0.0;
-    L[3][0] = 0.5 * (b2 - u * ci); L[3][1] = -0.5 * (b1 * u - ci); L[3][2] = -0.5 * b1 * v; L[3][3] = 0.5 * b1;
-    R[0][0] = 1.0;       R[0][1] = 1.0;      R[0][2] = 0.0; R[0][3] = 1.0;
-    R[1][0] = u - c;     R[1][1] = u;        R[1][2] = 0.0; R[1][3] = u + c;
-    R[2][0] = v;         R[2][1] = v;        R[2][2] = 1.0; R[2][3] = v;
-    R[3][0] = H - u * c; R[3][1] = 0.5 * q2; R[3][2] = v;   R[3][3] = H + u * c;
-  } else {
-    L[0][0] = 0.5 * (b2 + v * ci); L[0][1] = -0.5 * b1 * u; L[0][2] = -0.5 * (b1 * v + ci); L[0][3] = 0.5 * b1;
-    L[1][0] = 1.0 - b2;            L[1][1] = b1 * u;        L[1][2] = b1 * v;               L[1][3] = -b1;
-    L[2][0] = -u;                  L[2][1] = 1.0;           L[2][2] = 0.0;                  L[2][3] = 0.0;
-    L[3][0] = 0.5 * (b2 - v * ci); L[3][1] = -0.5 * b1 * u; L[3][2] = -0.5 * (b1 * v - ci); L[3][3] = 0.5 * b1;
-    R[0][0] = 1.0;       R[0][1] = 1.0;      R[0][2] = 0.0; R[0][3] = 1.0;
-    R[1][0] = u;         R[1][1] = u;        R[1][2] = 1.0; R[1][3] = u;
-    R[2][0] = v - c;     R[2][1] = v;        R[2][2] = 0.0; R[2][3] = v + c;
-    R[3][0] = H - v * c; R[3][1] = 0.5 * q2; R[3][2] = u;   R[3][3] = H + v * c;
-  }
-}
-
 // physical flux in direction DIR (0 = f, 1 = g) of the conserved state U
 template <int EQ, int NC, int DIR, class T>
 __device__ __forceinline__ void phys_flux(const SchemeParams& P, const T (&U)[NC], T (&F)[NC]) {

@@ -125,10 +125,10 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
       const double u = Uc[1] * rinv;
       const double pr = gm1 * (Uc[2] - 0.5 * Uc[1] * u);
       const double c2 = (gm1 + 1.0) * pr * rinv;
-      const double c = sqrt(c2);
-      const double ci = rcp_w<TR>(c);
+      const double ci = rsq_w<TR>(c2);
+      const double c = c2 * ci;
       const double H = (Uc[2] + pr) * rinv;
-      const double b1 = gm1 * rcp_w<TR>(c2);
+      const double b1 = gm1 * (ci * ci);
       const double b2 = 0.5 * b1 * u * u;
       // one field: project with row (l0, l1, l2), reconstruct, evaluate
       auto field = [&](double l0, double l1, double l2, double (&q)[5]) {

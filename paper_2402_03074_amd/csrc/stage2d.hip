@@ -50,10 +50,10 @@ __device__ __forceinline__ Prim make_prim(double gm1, const double (&U)[4]) {
   p.q2 = p.u * p.u + p.v * p.v;
   const double pr = gm1 * (U[3] - 0.5 * U[0] * p.q2);
   const double c2 = (gm1 + 1.0) * pr * rinv;
-  p.c = sqrt(c2);
-  p.ci = rcp_w<TR>(p.c);
+  p.ci = rsq_w<TR>(c2);
+  p.c = c2 * p.ci;
   p.H = (U[3] + pr) * rinv;
-  p.b1 = gm1 * rcp_w<TR>(c2);
+  p.b1 = gm1 * (p.ci * p.ci);
   p.b2 = 0.5 * p.b1 * p.q2;
   return p;
 }
