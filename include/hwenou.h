@@ -82,7 +82,14 @@ typedef struct hwenou_desc {
   double adv[2];    /* advection velocity */
   double gas_gamma; /* ratio of specific heats (Euler) */
   double gamma_low; /* linear weight of every linear polynomial (paper: 1/400) */
-  double eps;       /* epsilon of the nonlinear weights (paper: 1e-10) */
+  double eps;       /* epsilon of the nonlinear weights (paper: 1e-10), >= 0.
+                       The weights are evaluated with one reciprocal over the
+                       product of the five (2D) or three (1D) denominators
+                       beta_m u_ave + eps; that stays in FP64 range for
+                       reconstructed variables up to ~1e15 (2D) or ~1e25
+                       (1D) in magnitude, and an eps of the paper's size
+                       keeps it from underflowing.  Beyond, the state turns non-finite
+                       (ENONPHYSICAL). */
 } hwenou_desc;
 
 /* One instance: a uniform grid of nx x ny cells on [x0, x1] x [y0, y1]

@@ -177,8 +177,8 @@ __device__ __forceinline__ void combine_factors(const SchemeParams& P, const dou
   // ratios of these, so the scale cancels exactly.  d_m and tau scale like
   // the fourth power of the reconstructed variable, so tau P_m like its
   // (4 NM + 4)th: the products stay finite for variables below ~1e15 in
-  // magnitude (NM = 4; ~1e25 for NM = 2), and eps keeps them from
-  // underflowing.  Beyond that range the weights come out non-finite (the
+  // magnitude (NM = 4; ~1e25 for NM = 2), and an eps of the paper's size
+  // keeps them from underflowing.  Beyond that range the weights come out non-finite (the
   // per-field reciprocals of the plain form reach ~1e77).
   double d[NM + 1];
 #pragma unroll

@@ -51,9 +51,10 @@ def solver_for(P, precision="fp64", **kw):
         inst = H.make_inst(P.nx, P.ny, P.domain, bc)
     p = P.params
     weights = {0: "scale_invariant", 1: "zq", 2: "linear"}[p.weights]
-    return H.Solver(P.dim, P.eq, [inst], precision=precision, weights=weights,
-                    char_decomp=int(p.char_decomp), adv=(p.adv_x, p.adv_y),
-                    gas_gamma=p.gas_gamma, gamma_low=p.gamma_low, eps=p.eps, **kw)
+    opts = dict(weights=weights, char_decomp=int(p.char_decomp), adv=(p.adv_x, p.adv_y),
+                gas_gamma=p.gas_gamma, gamma_low=p.gamma_low, eps=p.eps)
+    opts.update(kw)
+    return H.Solver(P.dim, P.eq, [inst], precision=precision, **opts)
 
 
 def flat(P, u, m):
