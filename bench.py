@@ -302,6 +302,24 @@ def summary_roofline(case, r, precision, rec):
             "avg_launch_ms": kavg, "bytes_per_cell_stage": byts}, None
 
 
+def attach_traffic(roof, hbm, rec, precision, case, fresh):
+    """HBM bytes per launch measured by the committed counter summary
+    (calibrated FETCH_SIZE + WRITE_SIZE), when it was taken on the current
+    kernel source and on this workload; null otherwise.  With it, the measured
+    HBM rate over this run's launch time goes beside the algorithmic one."""
+    if roof["bound"] != "alu":
+        return
+    key = f"hbm_bytes_per_launch_{precision}"
+    roof["counters_current"] = fresh
+    roof["traffic"] = (float(rec[key]) if fresh and case.name == COUNTERS[case.dim][2]
+                       and key in rec else None)
+    if roof["traffic"] is not None and hbm is not None:
+        meas = roof["traffic"] / (roof["avg_launch_ms"] * 1e-3) / 1e9
+        hbm["achieved_measured"] = meas
+        hbm["frac_measured"] = meas / HBM_PEAK_GBS
+        hbm["measured_over_algorithmic"] = meas / hbm["achieved_algorithmic"]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -337,18 +355,7 @@ def main():
     head = precs[0]
     r = results[head]
     roof, hbm = summary_roofline(case, r, head, rec)
-    if roof["bound"] == "alu":
-        roof["counters_current"] = fresh
-        roof["traffic"] = (float(rec[f"hbm_bytes_per_launch_{head}"])
-                           if fresh and case.name == COUNTERS[case.dim][2]
-                           and f"hbm_bytes_per_launch_{head}" in rec else None)
-        if roof["traffic"] is not None and hbm is not None:
-            # measured HBM rate: calibrated FETCH_SIZE + WRITE_SIZE per launch
-            # over the launch time of this run
-            meas = roof["traffic"] / (roof["avg_launch_ms"] * 1e-3) / 1e9
-            hbm["achieved_measured"] = meas
-            hbm["frac_measured"] = meas / HBM_PEAK_GBS
-            hbm["measured_over_algorithmic"] = meas / hbm["achieved_algorithmic"]
+    attach_traffic(roof, hbm, rec, head, case, fresh)
     line = {
         "metric": METRIC if name == DEFAULT_WORKLOAD else "cell-stage updates/s",
         "value": r["rate"],
@@ -371,6 +378,7 @@ def main():
     for prec in precs[1:]:
         r2 = results[prec]
         roof2, hbm2 = summary_roofline(case, r2, prec, rec)
+        attach_traffic(roof2, hbm2, rec, prec, case, fresh)
         line[prec] = {"value": r2["rate"], "ms_per_step": r2["ms_per_step"],
                       "avg_stage_launch_ms": r2["stage_ms"], "roofline": roof2}
         if hbm2 is not None:

@@ -51,3 +51,28 @@ def test_profile_summaries_parse(dim):
         ex = float(rec[f"executed_flops_per_cell_stage_{prec}"])
         al = float(rec[f"algorithmic_flops_per_cell_stage_{prec}"])
         assert 0 < al < ex
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_traffic_reported_only_for_current_counters(precision):
+    """Measured HBM bytes enter the line only when the counters were taken on
+    the current kernel source and on the same workload, for either precision."""
+    class Case:
+        dim, name = 2, bench.COUNTERS[2][2]
+    rec = {f"hbm_bytes_per_launch_{precision}": "1.5e9"}
+
+    def roofline():
+        return ({"bound": "alu", "avg_launch_ms": 0.5},
+                {"achieved_algorithmic": 1000.0})
+    roof, hbm = roofline()
+    bench.attach_traffic(roof, hbm, rec, precision, Case, True)
+    assert roof["traffic"] == 1.5e9 and roof["counters_current"] is True
+    assert abs(hbm["achieved_measured"] - 3000.0) < 1e-9
+    assert abs(hbm["measured_over_algorithmic"] - 3.0) < 1e-12
+    roof, hbm = roofline()
+    bench.attach_traffic(roof, hbm, rec, precision, Case, False)  # stale source hash
+    assert roof["traffic"] is None and "achieved_measured" not in hbm
+    Case.name = "euler2d-batch64"  # counters were taken on another workload
+    roof, hbm = roofline()
+    bench.attach_traffic(roof, hbm, rec, precision, Case, True)
+    assert roof["traffic"] is None
