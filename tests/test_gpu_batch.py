@@ -167,21 +167,36 @@ def test_batch_instances_finish_at_their_own_final_time():
     S.close()
 
 
-def test_graph_replay_equals_eager_stages():
-    print("[gpu] graph vs eager", flush=True)
-    n = 96
-    u0, m0 = W.euler_2d_vortex_quadrant(n, seed=5200, q=2)
-    P = Problem(2, "euler", (n, n), (0, 10, 0, 10))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_graph_replay_equals_eager_stages(dim, precision):
+    """Graph replays take each step's alpha from the wave speeds that the
+    stage-2 kernel reduces while it writes the step's result; the eager
+    stages here take it from the separate max-wave-speed kernel.  Equal
+    states after 5 steps pin the fused reduction bitwise."""
+    print(f"[gpu] graph vs eager dim={dim} {precision}", flush=True)
+    if dim == 1:
+        n = 3000
+        u0, m0 = W.euler_1d_shocktube(n, seed=5201)
+        P = Problem(1, "euler", n, (0, 1), bc="transmissive")
+        dx = 1.0 / n
+    else:
+        n = 96
+        u0, m0 = W.euler_2d_vortex_quadrant(n, seed=5200, q=2)
+        P = Problem(2, "euler", (n, n), (0, 10, 0, 10))
+        dx = 10.0 / n
     uf, mf = flat(P, u0, m0)
-    S = solver_for(P)
-    ua, ma = to_gpu(uf), to_gpu(mf)
+    S = solver_for(P, precision=precision)
+    mdt = S.mom_dtype
+    ua, ma = to_gpu(uf), to_gpu(mf, mdt)
     S.advance(ua, ma, 0.6, 1e30, 5)
-    ub, mb = to_gpu(uf), to_gpu(mf)
-    dx = 10.0 / n
+    ub, mb = to_gpu(uf), to_gpu(mf, mdt)
     for _ in range(5):
         alpha = S.max_wavespeed(ub)
         a = alpha.cpu().numpy()[0]
-        dt = torch.tensor([0.6 / (a[0] / dx + a[1] / dx)], dtype=torch.float64, device="cuda")
+        # the device's time step, in its order of operations
+        step = 0.6 * dx / a[0] if dim == 1 else 0.6 / (a[0] / dx + a[1] / dx)
+        dt = torch.tensor([step], dtype=torch.float64, device="cuda")
         u1, m1 = S.empty_state()
         u2, m2 = S.empty_state()
         S.stage(0, dt, alpha, ub, mb, u1, m1)
