@@ -110,10 +110,7 @@ def test_advection_to_final_time_matches_oracle():
     S.close()
 
 
-@pytest.mark.parametrize("case", [c for c in CASES if c[0] in
-                                  ("euler1d_tube_1000", "euler2d_quad_130x96", "burgers2d_70",
-                                   "euler2d_quad_130x70_single")],
-                         ids=lambda c: c[0])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_one_stage_mixed(case):
     name, P, u0, m0 = case
     print(f"[gpu] one-stage mixed {name}", flush=True)
@@ -124,10 +121,26 @@ def test_one_stage_mixed(case):
     # the mixed path stores moments in FP32: feed it the rounded moments
     got = gpu_three_stages(S, P, u0, m0.astype(np.float32).astype(np.float64), dt, alpha,
                            inputs=ref[:2])
+    # The moments are formed in FP32 as v^ + dt F2, whose flux terms are of size
+    # (dt/h) |f| with |f| <= (1 + alpha) max|U|: their rounding, not the
+    # moments' own size, sets the error where the moments are small.
+    h = (P.dx,) if P.dim == 1 else (P.dx, P.dy)
+    scale = (1.0 + max(alpha)) * max(np.abs(u0).max(), 1e-300)
     for s in range(3):
-        eu, em = state_err(P, got[s], ref[s])
-        # averages: FP32 fluxes times dt/dx; moments: FP32 storage
-        assert eu <= 2e-6 and em <= 2e-5, (name, s, eu, em)
+        eu, _ = state_err(P, got[s], ref[s])
+        # averages: FP32 fluxes times dt/dx
+        assert eu <= 2e-6, (name, s, eu)
+        gm, rm = got[s][1], ref[s][1]
+        worst = 0.0
+        for d in range(P.dim):
+            for k in range(P.ncomp):
+                err = np.abs(gm[d, k] - rm[d, k]).max()
+                worst = max(worst, err / (dt / h[d] * scale))
+                # measured: at most 1.1e-7 of the flux scale (~2 FP32 roundings)
+                assert err <= 2e-5 * np.abs(rm[d, k]).max() + 1e-6 * dt / h[d] * scale, \
+                    (name, s, d, k, err)
+        print(f"[gpu] mixed {name} stage {s}: averages {eu:.1e}, moments {worst:.1e} "
+              f"of the flux scale", flush=True)
     S.close()
 
 
