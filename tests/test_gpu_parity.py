@@ -73,10 +73,7 @@ def test_one_stage_fp64(case):
     S.close()
 
 
-@pytest.mark.parametrize("case", [c for c in CASES if c[0] in
-                                  ("adv1d_sine_200", "euler1d_tube_1000", "burgers2d_70",
-                                   "euler2d_quad_70x64_trans", "euler2d_quad_130x70_single")],
-                         ids=lambda c: c[0])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_100_steps_fp64(case):
     import torch
     name, P, u0, m0 = case
