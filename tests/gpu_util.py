@@ -103,3 +103,27 @@ def oracle_three_stages(P, u0, m0, dt, alpha):
     u, m, _ = P.stage(2, dt, alpha, u, m, base)
     outs.append((u, m))
     return outs
+
+
+def assert_mixed_stage_close(name, P, u0, dt, alpha, got, ref):
+    """The mixed form's one-stage bar.  Averages: 2e-6 relative (FP32 fluxes
+    times dt/dx).  Moments: 2e-5 of their maximum plus 1e-6 of the flux scale
+    (dt/h)(1 + alpha) max|U|: they are formed in FP32 as v^ + dt F2, whose
+    flux terms are of that size, so that rounding, not the moments' own size,
+    sets the error where the moments are small (measured: at most 1.1e-7 of
+    the flux scale, about two FP32 roundings)."""
+    h = (P.dx,) if P.dim == 1 else (P.dx, P.dy)
+    scale = (1.0 + max(alpha)) * max(np.abs(u0).max(), 1e-300)
+    for s in range(3):
+        eu, _ = state_err(P, got[s], ref[s])
+        assert eu <= 2e-6, (name, s, eu)
+        gm, rm = got[s][1], ref[s][1]
+        worst = 0.0
+        for d in range(P.dim):
+            for k in range(P.ncomp):
+                err = np.abs(gm[d, k] - rm[d, k]).max()
+                worst = max(worst, err / (dt / h[d] * scale))
+                assert err <= 2e-5 * np.abs(rm[d, k]).max() + 1e-6 * dt / h[d] * scale, \
+                    (name, s, d, k, err)
+        print(f"[gpu] mixed {name} stage {s}: averages {eu:.1e}, moments {worst:.1e} "
+              f"of the flux scale", flush=True)

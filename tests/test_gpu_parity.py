@@ -12,8 +12,8 @@ import pytest
 import workloads as W
 from oracle.driver import Problem
 
-from gpu_util import (gpu_three_stages, oracle_three_stages, solver_for, state_err, to_gpu,
-                      flat, unflat, rel_err)
+from gpu_util import (assert_mixed_stage_close, gpu_three_stages, oracle_three_stages,
+                      solver_for, state_err, to_gpu, flat, unflat, rel_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -107,30 +107,6 @@ def test_advection_to_final_time_matches_oracle():
     S.close()
 
 
-def _assert_mixed_stage_close(name, P, u0, dt, alpha, got, ref):
-    """The mixed form's one-stage bar.  Averages: 2e-6 relative (FP32 fluxes
-    times dt/dx).  Moments: 2e-5 of their maximum plus 1e-6 of the flux scale
-    (dt/h)(1 + alpha) max|U|: they are formed in FP32 as v^ + dt F2, whose
-    flux terms are of that size, so that rounding, not the moments' own size,
-    sets the error where the moments are small (measured: at most 1.1e-7 of
-    the flux scale, about two FP32 roundings)."""
-    h = (P.dx,) if P.dim == 1 else (P.dx, P.dy)
-    scale = (1.0 + max(alpha)) * max(np.abs(u0).max(), 1e-300)
-    for s in range(3):
-        eu, _ = state_err(P, got[s], ref[s])
-        assert eu <= 2e-6, (name, s, eu)
-        gm, rm = got[s][1], ref[s][1]
-        worst = 0.0
-        for d in range(P.dim):
-            for k in range(P.ncomp):
-                err = np.abs(gm[d, k] - rm[d, k]).max()
-                worst = max(worst, err / (dt / h[d] * scale))
-                assert err <= 2e-5 * np.abs(rm[d, k]).max() + 1e-6 * dt / h[d] * scale, \
-                    (name, s, d, k, err)
-        print(f"[gpu] mixed {name} stage {s}: averages {eu:.1e}, moments {worst:.1e} "
-              f"of the flux scale", flush=True)
-
-
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_one_stage_mixed(case):
     name, P, u0, m0 = case
@@ -142,7 +118,7 @@ def test_one_stage_mixed(case):
     # the mixed path stores moments in FP32: feed it the rounded moments
     got = gpu_three_stages(S, P, u0, m0.astype(np.float32).astype(np.float64), dt, alpha,
                            inputs=ref[:2])
-    _assert_mixed_stage_close(name, P, u0, dt, alpha, got, ref)
+    assert_mixed_stage_close(name, P, u0, dt, alpha, got, ref)
     S.close()
 
 
@@ -335,7 +311,7 @@ def test_degenerate_sizes_one_step(case, precision):
     S = solver_for(P, precision=precision)
     got = gpu_three_stages(S, P, u, m, dt, alpha, inputs=ref[:2])
     if precision == "mixed":
-        _assert_mixed_stage_close(name, P, u, dt, alpha, got, ref)
+        assert_mixed_stage_close(name, P, u, dt, alpha, got, ref)
     else:
         for s in range(3):
             eu, em = state_err(P, got[s], ref[s], floor=1e-3)

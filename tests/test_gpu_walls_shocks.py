@@ -2,8 +2,10 @@
 run to their final times on the GPU.
 
 Walls: one stage and 100 steps of the HIP path against the oracle (FP64:
-relative L-infinity <= 1e-12 / 1e-10), the mixed form at the one-stage
-tolerances of the other mixed tests, and the GPU's reflective problem
+relative L-infinity <= 1e-12 after one stage; after 100 steps <= 1e-10, or
+ten times the oracle's own one-ulp sensitivity where reflected shocks
+amplify rounding, with conservation of mass and energy checked besides),
+the mixed form at the one-stage bar of the other mixed tests, and the GPU's reflective problem
 against its own mirror-extended periodic problem (bitwise: the kernels see
 the same stencil values).
 
@@ -20,8 +22,8 @@ import pytest
 import workloads as W
 from oracle.driver import Problem
 
-from gpu_util import (gpu_three_stages, oracle_three_stages, solver_for, state_err, to_gpu,
-                      flat, unflat)
+from gpu_util import (assert_mixed_stage_close, gpu_three_stages, oracle_three_stages,
+                      solver_for, state_err, to_gpu, flat, unflat)
 
 pytestmark = pytest.mark.gpu
 
@@ -71,39 +73,52 @@ def test_walls_one_stage_fp64(case):
     S.close()
 
 
-@pytest.mark.parametrize("case", [c for c in WALLS if c[0] in ("tube1d_300", "quad2d_70x45_walls")],
-                         ids=lambda c: c[0])
+@pytest.mark.parametrize("case", WALLS, ids=[c[0] for c in WALLS])
 def test_walls_one_stage_mixed(case):
     name, P, u0, m0 = case
     print(f"[gpu] walls one-stage mixed {name}", flush=True)
+    m0 = m0.astype(np.float32).astype(np.float64)  # the moments the mixed form stores
     alpha = P.max_wavespeed(u0)
     dt = P.dt_from(alpha, 0.6)
     ref = oracle_three_stages(P, u0, m0, dt, alpha)
     S = solver_for(P, precision="mixed")
-    got = gpu_three_stages(S, P, u0, m0.astype(np.float32).astype(np.float64), dt, alpha,
-                           inputs=ref[:2])
-    for s in range(3):
-        eu, em = state_err(P, got[s], ref[s])
-        assert eu <= 2e-6 and em <= 2e-5, (name, s, eu, em)
+    got = gpu_three_stages(S, P, u0, m0, dt, alpha, inputs=ref[:2])
+    assert_mixed_stage_close(name, P, u0, dt, alpha, got, ref)
     S.close()
 
 
-@pytest.mark.parametrize("case", [c for c in WALLS if c[0] in ("tube1d_300", "quad2d_70x45_walls")],
-                         ids=lambda c: c[0])
+@pytest.mark.parametrize("case", WALLS, ids=[c[0] for c in WALLS])
 def test_walls_100_steps_fp64(case):
+    """100 FP64 steps against the oracle.  Shocks reflected at walls can
+    amplify rounding: on the 64^2 component-wise case a one-ulp change of the
+    oracle's own input moves its result by ~1e-4 after 100 steps.  So the bar
+    is max(1e-10, ten times that sensitivity), measured here per case, and
+    the walls' conservation of mass and energy (their fluxes through a wall
+    cancel) is checked on the GPU result independently of it."""
     import torch
     name, P, u0, m0 = case
     print(f"[gpu] walls 100 steps {name}", flush=True)
     uo, mo, t, steps = P.advance(u0, m0, cfl=0.6, max_steps=100)
+    up, mp, tp, _ = P.advance(np.nextafter(u0, np.inf), m0, cfl=0.6, max_steps=100)
+    su, sm = state_err(P, (up, mp), (uo, mo))
+    st = abs(tp - t) / t
     S = solver_for(P)
     uf, mf = flat(P, u0, m0)
     ug, mg = to_gpu(uf), to_gpu(mf)
     tg, sg = S.advance(ug, mg, 0.6, 1e30, 100)
     torch.cuda.synchronize()
-    assert sg == [100] and abs(tg[0] - t) <= 1e-12 * t
-    eu, em = state_err(P, unflat(P, ug.cpu().numpy(), mg.cpu().numpy()), (uo, mo))
-    print(f"[gpu]   {name}: {eu:.2e} {em:.2e}", flush=True)
-    assert eu <= 1e-10 and em <= 1e-10, (name, eu, em)
+    got_u = ug.cpu().numpy()
+    eu, em = state_err(P, unflat(P, got_u, mg.cpu().numpy()), (uo, mo))
+    print(f"[gpu]   {name}: {eu:.2e} {em:.2e}, t {abs(tg[0] - t) / t:.1e}; oracle "
+          f"sensitivity {su:.1e} {sm:.1e}, t {st:.1e}", flush=True)
+    assert sg == [100] and abs(tg[0] - t) <= max(1e-12, 10.0 * st) * t, (name, tg, t)
+    assert eu <= max(1e-10, 10.0 * su) and em <= max(1e-10, 10.0 * sm), (name, eu, em, su, sm)
+    # mass and energy: no flux through walls or periodic sides (outflow
+    # sides, BC code 1, let them through)
+    if 1 not in tuple(P.bc):
+        for k in (0, P.ncomp - 1):
+            tot0, tot1 = uf[k].sum(), got_u[k].sum()
+            assert abs(tot1 - tot0) <= 1e-12 * np.abs(uf[k]).sum(), (name, k, tot0, tot1)
     S.close()
 
 
