@@ -251,6 +251,41 @@ def test_full_batch_1d_sampled_instances():
     S.close()
 
 
+def test_full_batch_2d_sampled_instances():
+    """The 64-instance 2D batch (grids of 256^2 to 1024^2, 22 M cells) in one
+    handle, at the default launch shape (results do not depend on it, see
+    test_launch_shape_invariance): one step, then the smallest, a median and
+    the largest instance compared whole with the oracle."""
+    import torch
+    import paper_2402_03074_amd as H
+    print("[gpu] full 2D batch sampled parity: generating", flush=True)
+    sides, data = W.batch_2d_euler()
+    insts, off = [], 0
+    for side in sides:
+        insts.append(H.make_inst(int(side), int(side), (0.0, 10.0, 0.0, 10.0), "periodic",
+                                 offset=off))
+        off += int(side) ** 2
+    u = np.concatenate([d[0].reshape(4, -1) for d in data], axis=1)
+    m = np.concatenate([d[1].reshape(2, 4, -1) for d in data], axis=2)
+    S = H.Solver(2, "euler", insts)
+    ug, mg = to_gpu(u), to_gpu(m)
+    S.advance(ug, mg, 0.6, 1e30, 1)
+    torch.cuda.synchronize()
+    got_u, got_m = ug.cpu().numpy(), mg.cpu().numpy()
+    S.close()
+    del ug, mg
+    order = np.argsort(sides, kind="stable")
+    for k in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        n = int(sides[k])
+        print(f"[gpu] full 2D batch: instance {k} ({n}^2) against the oracle", flush=True)
+        a, b = insts[k].offset, insts[k].offset + n * n
+        P = Problem(2, "euler", (n, n), (0.0, 10.0, 0.0, 10.0))
+        uo, mo, _, _ = P.advance(data[k][0], data[k][1], cfl=0.6, max_steps=1)
+        got = (got_u[:, a:b].reshape(4, n, n), got_m[:, :, a:b].reshape(2, 4, n, n))
+        eu, em = state_err(P, got, (uo, mo))
+        assert eu <= TOL_STAGE * 10 and em <= TOL_STAGE * 10, (k, n, eu, em)
+
+
 @pytest.mark.parametrize("weights", ["zq", "linear"])
 @pytest.mark.parametrize("dim", [1, 2])
 def test_weight_modes_one_step(weights, dim):
