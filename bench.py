@@ -282,7 +282,8 @@ def mesh_difference(H, W, torch, np, n, t_final):
 def summary_roofline(case, r, precision, rec):
     """Roofline position of the stage kernel: against the vector ALU peak
     when its flops per cell-stage have been counted (both stage kernels are
-    bound by instruction issue), with the algorithmic HBM view beside it."""
+    limited by their vector instruction stream and its latencies, far below
+    the HBM roof), with the algorithmic HBM view beside it."""
     cells = case.cells
     kavg = r["stage_ms"]
     kernel = COUNTERS[case.dim][0]
