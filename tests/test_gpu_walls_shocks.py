@@ -122,6 +122,65 @@ def test_walls_100_steps_fp64(case):
     S.close()
 
 
+_DIR_BC = [("periodic", "periodic"), ("transmissive", "transmissive"),
+           ("reflective", "reflective"), ("transmissive", "reflective"),
+           ("reflective", "transmissive")]
+_ABBR = {"periodic": "P", "transmissive": "T", "reflective": "R"}
+BC_SWEEP = [(bx, by) for bx in _DIR_BC for by in _DIR_BC]
+
+
+@pytest.mark.parametrize("bx,by", BC_SWEEP,
+                         ids=["".join(_ABBR[b] for b in bx + by) for bx, by in BC_SWEEP])
+def test_boundary_combinations_one_stage(bx, by):
+    """Every pairing of periodic, outflow and wall sides in x and y (periodic
+    sides paired), on a 67 x 13 grid: two strips, the second of 5 columns.
+    One stage against the oracle, FP64 at the one-stage bar and the mixed
+    form at its bar."""
+    name = "".join(_ABBR[b] for b in bx + by)
+    print(f"[gpu] boundary combination {name}", flush=True)
+    u, m = W.euler_2d_vortex_quadrant(67, 13, seed=3300 + BC_SWEEP.index((bx, by)), q=2)
+    P = Problem(2, "euler", (67, 13), (0, 10, 0, 10), bc=bx + by)
+    alpha = P.max_wavespeed(u)
+    dt = P.dt_from(alpha, 0.6)
+    ref = oracle_three_stages(P, u, m, dt, alpha)
+    S = solver_for(P)
+    got = gpu_three_stages(S, P, u, m, dt, alpha, inputs=ref[:2])
+    S.close()
+    for s in range(3):
+        eu, em = state_err(P, got[s], ref[s], floor=1e-3)
+        assert eu <= 1e-12 and em <= 1e-12, (name, s, eu, em)
+    m32 = m.astype(np.float32).astype(np.float64)
+    ref = oracle_three_stages(P, u, m32, dt, alpha)
+    S = solver_for(P, precision="mixed")
+    got = gpu_three_stages(S, P, u, m32, dt, alpha, inputs=ref[:2])
+    S.close()
+    assert_mixed_stage_close(name, P, u, dt, alpha, got, ref)
+
+
+@pytest.mark.parametrize("bx", _DIR_BC, ids=["".join(_ABBR[b] for b in bx) for bx in _DIR_BC])
+def test_boundary_combinations_one_stage_1d(bx):
+    """The same pairings in 1D, on 67 cells: two tiles, the second of 5."""
+    name = "1d_" + "".join(_ABBR[b] for b in bx)
+    print(f"[gpu] boundary combination {name}", flush=True)
+    u, m = W.random_smooth_1d(67, 3, seed=3400 + _DIR_BC.index(bx), positive_euler=True)
+    P = Problem(1, "euler", 67, (0, 1), bc=bx)
+    alpha = P.max_wavespeed(u)
+    dt = P.dt_from(alpha, 0.6)
+    ref = oracle_three_stages(P, u, m, dt, alpha)
+    S = solver_for(P)
+    got = gpu_three_stages(S, P, u, m, dt, alpha, inputs=ref[:2])
+    S.close()
+    for s in range(3):
+        eu, em = state_err(P, got[s], ref[s], floor=1e-3)
+        assert eu <= 1e-12 and em <= 1e-12, (name, s, eu, em)
+    m32 = m.astype(np.float32).astype(np.float64)
+    ref = oracle_three_stages(P, u, m32, dt, alpha)
+    S = solver_for(P, precision="mixed")
+    got = gpu_three_stages(S, P, u, m32, dt, alpha, inputs=ref[:2])
+    S.close()
+    assert_mixed_stage_close(name, P, u, dt, alpha, got, ref)
+
+
 def _mirror_x(u, m):
     sgn = np.ones(u.shape[0])
     sgn[1] = -1.0
