@@ -12,14 +12,19 @@ SRC = os.path.join(HERE, "hwenou_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose=False):
+def build(verbose=False, out=None, plant=0):
+    """Compile the oracle into `out` (default: oracle/liboracle.so).  `plant`
+    selects one of the known mistakes of the ORACLE_PLANT switch; the tests
+    build such variants elsewhere to show that the pins fail on them."""
+    lib = out or LIB
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas", SRC, "-o", LIB + ".tmp", "-lm"]
+           "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas", f"-DORACLE_PLANT={int(plant)}",
+           SRC, "-o", lib + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

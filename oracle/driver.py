@@ -58,7 +58,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         from . import build
         build.build()
-    L = C.CDLL(LIB_PATH)
+    _lib = load(LIB_PATH)
+    return _lib
+
+
+def load(path):
+    """Load a built oracle library and hand it the derived operators."""
+    L = C.CDLL(path)
     dp = C.POINTER(C.c_double)
     L.oracle_rhs_1d.argtypes = [C.POINTER(_Params), C.c_int, C.c_double, C.c_int, C.c_int,
                                 C.c_double, dp, dp, dp, dp, dp]
@@ -68,6 +74,7 @@ def lib():
     L.oracle_all_physical.argtypes = [C.POINTER(_Params), C.c_int, C.c_size_t, dp]
     L.oracle_num_threads.restype = C.c_int
     L.oracle_set_num_threads.argtypes = [C.c_int]
+    L.oracle_eigvecs.argtypes = [C.POINTER(_Params), dp, C.c_int, C.c_int, dp, dp]
     # hand in the exactly derived operators
     r1 = derive.recon_1d()
     keep = [_flat(r1["M0"]), _flat(r1["M1"]), _flat(r1["M2"]), _flat(derive.beta_gram_1d(4)),
@@ -84,8 +91,26 @@ def lib():
              np.array([float(v) for v in qv1]), np.array([float(v) for v in qw1])]
     L.oracle_set_ops_2d(*[np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(dp)
                           for a in keep2])
-    _lib = L
     return L
+
+
+class using:
+    """Context manager: route every oracle call through another loaded
+    library (a planted variant built by the tests), then restore."""
+
+    def __init__(self, L):
+        self.L = L
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = self.L
+        return self.L
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
 
 
 def num_threads():
@@ -204,6 +229,19 @@ class Problem:
             return u_new, m_new, (np.array(ubar, dtype=np.float64, copy=True), mh)
         a, b = ((0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))[s - 1]
         return a * base[0] + b * u_new, a * base[1] + b * m_new, base
+
+    def eigvecs(self, U, direction=0):
+        """(R, L): the right eigenvectors (columns) the reconstruction
+        projects with at the conserved state U, and L = R^-1 (Euler)."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        n = self.dim + 2
+        R = np.zeros(n * n)
+        Linv = np.zeros(n * n)
+        rc = lib().oracle_eigvecs(C.byref(self.params), _ptr(U), self.dim, int(direction),
+                                  _ptr(R), _ptr(Linv))
+        if rc == ERR_NONPHYSICAL:
+            raise NonPhysicalState("non-physical state")
+        return R.reshape(n, n), Linv.reshape(n, n)
 
     def check_physical(self, ubar):
         ubar = np.ascontiguousarray(ubar, dtype=np.float64)

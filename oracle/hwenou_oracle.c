@@ -24,7 +24,16 @@
  * f') yields the x-edge values, the interior values used for f and v^, and a
  * y-sweep (eigenvectors of g') the y-edge values, the interior values used
  * for g and w^.  L = R^{-1} is obtained here by Gauss-Jordan elimination.
+ *
+ * ORACLE_PLANT (test-only compile switch, never set in the library that the
+ * tests and the benchmark load) plants one known mistake, so that the tests
+ * can show that a pin fails on it: 1 = energy entry q^2 instead of q^2/2 in the
+ * entropy eigenvector; 2 = the 2D tau averaged over 2 instead of the 4
+ * differences; 3 = the 2D u_ave taken over all nine stencil cells.
  */
+#ifndef ORACLE_PLANT
+#define ORACLE_PLANT 0
+#endif
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -152,7 +161,7 @@ static void nonlinear_weights(const oracle_params *P, const double *beta, int nm
   if (P->weights == W_ZQ) u_ave = 1.0;
   double t = 0.0;
   for (int m = 1; m <= nm; ++m) t += fabs(beta[0] - beta[m]);
-  t /= nm;
+  t /= (ORACLE_PLANT == 2 && nm == 4) ? 2 : nm;
   double tau = t * t;
   double sum = 0.0;
   for (int m = 0; m <= nm; ++m) {
@@ -253,24 +262,36 @@ static int euler_right_eigvecs(const oracle_params *P, const double *U, int dim,
   double c = sqrt(gm * p / rho);
   double H = (E + p) / rho;
   if (dim == 1) {
-    double cols[3][3] = {{1.0, u - c, H - u * c}, {1.0, u, 0.5 * u * u}, {1.0, u + c, H + u * c}};
+    const double e1 = ORACLE_PLANT == 1 ? u * u : 0.5 * u * u;
+    double cols[3][3] = {{1.0, u - c, H - u * c}, {1.0, u, e1}, {1.0, u + c, H + u * c}};
     for (int r = 0; r < 3; ++r)
       for (int k = 0; k < 3; ++k) R[r * 3 + k] = cols[k][r];
   } else if (dir == 0) {
+    const double e1 = ORACLE_PLANT == 1 ? q2 : 0.5 * q2;
     double cols[4][4] = {{1.0, u - c, v, H - u * c},
-                         {1.0, u, v, 0.5 * q2},
+                         {1.0, u, v, e1},
                          {0.0, 0.0, 1.0, v},
                          {1.0, u + c, v, H + u * c}};
     for (int r = 0; r < 4; ++r)
       for (int k = 0; k < 4; ++k) R[r * 4 + k] = cols[k][r];
   } else {
+    const double e1 = ORACLE_PLANT == 1 ? q2 : 0.5 * q2;
     double cols[4][4] = {{1.0, u, v - c, H - v * c},
-                         {1.0, u, v, 0.5 * q2},
+                         {1.0, u, v, e1},
                          {0.0, 1.0, 0.0, u},
                          {1.0, u, v + c, H + v * c}};
     for (int r = 0; r < 4; ++r)
       for (int k = 0; k < 4; ++k) R[r * 4 + k] = cols[k][r];
   }
+  return 0;
+}
+
+/* The eigenvector basis the reconstruction projects with, for the tests:
+ * R (right eigenvectors as columns, row-major n x n) and L = R^{-1}, at the
+ * conserved state U (n = dim + 2).  Returns 0, or ERR_NONPHYSICAL. */
+int oracle_eigvecs(const oracle_params *P, const double *U, int dim, int dir, double *R,
+                   double *L) {
+  if (euler_right_eigvecs(P, U, dim, dir, R) || invert(R, L, dim + 2)) return ERR_NONPHYSICAL;
   return 0;
 }
 
@@ -482,6 +503,11 @@ static void recon_2d_scalar(const oracle_params *P, const double d[17], double p
   for (int m = 0; m < 4; ++m) beta[m + 1] = quad_form(OP2_G1, cm[m], 3);
   /* u_ave over cells 2, 4, 5, 6, 8 */
   double ua = (fabs(d[1]) + fabs(d[3]) + fabs(d[4]) + fabs(d[5]) + fabs(d[7])) / 5.0;
+  if (ORACLE_PLANT == 3) {
+    ua = 0.0;
+    for (int t = 0; t < 9; ++t) ua += fabs(d[t]);
+    ua /= 9.0;
+  }
   double u_ave = ua * ua;
   double g0 = 1.0 - 4.0 * P->gamma_low;
   double lin[5] = {g0, P->gamma_low, P->gamma_low, P->gamma_low, P->gamma_low};
