@@ -85,11 +85,10 @@ typedef struct hwenou_desc {
   double eps;       /* epsilon of the nonlinear weights (paper: 1e-10), >= 0.
                        The weights are evaluated with one reciprocal over the
                        product of the five (2D) or three (1D) denominators
-                       beta_m u_ave + eps; that stays in FP64 range for
-                       reconstructed variables up to ~1e15 (2D) or ~1e25
-                       (1D) in magnitude, and an eps of the paper's size
-                       keeps it from underflowing.  Beyond, the state turns non-finite
-                       (ENONPHYSICAL). */
+                       beta_m u_ave + eps, scaled first by the power of two
+                       that brings the quartic's denominator into [1, 2), so
+                       the range follows the spread of the denominators, not
+                       the magnitude of the state. */
 } hwenou_desc;
 
 /* One instance: a uniform grid of nx x ny cells on [x0, x1] x [y0, y1]
@@ -145,22 +144,38 @@ int hwenou_max_wavespeed(hwenou_handle* h, const double* ubar, double* alpha_dev
 int hwenou_stage(hwenou_handle* h, int s, const double* dt_dev, const double* alpha_dev,
                  const double* ubar_in, const void* mom_in, double* ubar_out, void* mom_out);
 
-/* Advance every instance in place until t_final or max_steps steps.  Each
- * step takes alpha from the cell averages of U^n, dt = min(CFL dx / alpha,
- * t_final - t) (1D) or CFL / (alpha_1/dx + alpha_2/dy) clipped likewise (2D),
- * or dt = t_final - t when every wave speed of the instance is zero (all
- * fluxes vanish), and runs the three stages.  Whole steps (the three stages
- * and a finish kernel that also sets the next dt) are replayed from a
- * captured HIP graph, with alpha and dt on the device.  Synchronises once at
- * the end (plus one small read-back per 32 steps to stop early).  t_out
- * [n_inst] and steps_out [n_inst] are host arrays (may be NULL).  Errors: EINVAL (cfl <= 0,
- * t_final < 0, max_steps < 0), ENONPHYSICAL (some instance left the
- * physical states; the arrays hold the last step), EHIP. */
+/* Advance every instance in place until t_final or max_steps steps, with the
+ * modified SSP-RK3 of Eq. (2.13) (Section 2.1, Step 4; Section 2.2, Step 4).
+ * Each step takes alpha = max |f'(u)| (Lax-Friedrichs coefficient of
+ * Eq. (2.4)) from the cell averages of U^n and the time step
+ * dt = min(CFL dx / alpha, t_final - t) (1D) or CFL / (alpha_1/dx +
+ * alpha_2/dy) clipped likewise (2D), or dt = t_final - t when every wave
+ * speed of the instance is zero (all fluxes vanish).  The paper fixes the
+ * CFL number (0.6 in Section 3) but not the formula; this is the usual one.
+ * Whole steps (the three stages and a finish kernel that also sets the next
+ * dt) are replayed from a HIP graph, with alpha and dt on the device; the
+ * graph is captured on the first call and kept while the state pointers and
+ * the launch shape stay the same.  The host reads a completion flag after
+ * each chunk of steps without waiting for the chunk in flight, and
+ * synchronises at the end.  An instance whose state leaves the physical
+ * states (rho <= 0, p <= 0 or non-finite, flagged by any of its kernels)
+ * stops after the step in which that happened: its t_out and steps_out
+ * include that step, its arrays hold that step's result, and the other
+ * instances go on.  t_out [n_inst] and steps_out [n_inst] are host arrays
+ * (may be NULL).  Errors: EINVAL (cfl <= 0, t_final < 0, max_steps < 0,
+ * misaligned pointer), ENONPHYSICAL (some instance stopped that way;
+ * hwenou_inst_status tells which), EHIP. */
 int hwenou_advance(hwenou_handle* h, double* ubar, void* mom, double cfl, double t_final,
                    int max_steps, double* t_out, int* steps_out);
 
-/* Read and clear the handle's status flag (synchronous): HWENOU_OK or
- * HWENOU_ENONPHYSICAL. */
+/* Read and clear the per-instance status flags (synchronous): flags[k]
+ * (host array [n_inst], may be NULL) is 1 if a kernel found a non-physical or
+ * non-finite state of instance k since the flags were last cleared (by this
+ * call, hwenou_status or the start of hwenou_advance), else 0.  Returns
+ * HWENOU_OK, HWENOU_ENONPHYSICAL if any flag was set, or EHIP. */
+int hwenou_inst_status(hwenou_handle* h, int* flags);
+
+/* hwenou_inst_status without the per-instance flags. */
 int hwenou_status(hwenou_handle* h);
 
 /* Launch configuration of the stage kernels: waves per compute unit of the

@@ -12,8 +12,14 @@ Functions with the C-ABI's names:
   hwenou_max_wavespeed(handle, ubar, alpha)
   hwenou_stage(handle, s, dt, alpha, ubar_in, mom_in, ubar_out, mom_out)
   hwenou_advance(handle, ubar, mom, cfl, t_final, max_steps) -> (t, steps)
+  hwenou_status(handle), hwenou_inst_status(handle) -> flags
   hwenou_strerror(code)
 and a convenience wrapper `Solver`.
+
+The C-ABI takes bare device pointers and cannot check what they point to, so
+every wrapper checks its tensors first (GPU tensor on the handle's device,
+dtype, contiguity, element count of the handle's layout) and raises
+HwenouError(HWENOU_EINVAL) before anything is launched.
 """
 import ctypes as C
 import os
@@ -31,14 +37,15 @@ BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 CHAR = {"component": 0, "split": 1, "single": 2}
 
 EXPORTS = ["hwenou_create", "hwenou_destroy", "hwenou_strerror", "hwenou_max_wavespeed",
-           "hwenou_stage", "hwenou_advance", "hwenou_status", "hwenou_set_launch",
-           "hwenou_autotune"]
+           "hwenou_stage", "hwenou_advance", "hwenou_status", "hwenou_inst_status",
+           "hwenou_set_launch", "hwenou_autotune"]
 
 
 class HwenouError(RuntimeError):
-    def __init__(self, code, where):
+    def __init__(self, code, where, detail=""):
         self.code = code
-        super().__init__(f"{where}: {strerror(code)} (code {code})")
+        extra = f" ({detail})" if detail else ""
+        super().__init__(f"{where}: {strerror(code)}{extra} (code {code})")
 
 
 class NonPhysicalState(HwenouError):
@@ -79,6 +86,7 @@ def lib():
     L.hwenou_advance.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_int,
                                  C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.hwenou_status.argtypes = [vp]
+    L.hwenou_inst_status.argtypes = [vp, C.POINTER(C.c_int)]
     L.hwenou_set_launch.argtypes = [vp, C.c_int, C.c_int]
     L.hwenou_autotune.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     for name in EXPORTS:
@@ -107,6 +115,56 @@ def _check(rc, where):
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+class Geometry:
+    """What a handle's kernels address: dim, components, plane length (cells
+    per component plane), instances and the moment dtype ('float64' or
+    'float32'), and the device the handle was created on."""
+
+    def __init__(self, desc, instances, device=None):
+        self.dim = int(desc.dim)
+        self.ncomp = 1 if desc.eq != EQ["euler"] else self.dim + 2
+        self.n_inst = len(instances)
+        self.plane = max(int(I.offset) + int(I.nx) * (int(I.ny) if self.dim == 2 else 1)
+                         for I in instances)
+        self.mom_dtype = "float32" if desc.precision == PRECISION["mixed"] else "float64"
+        self.device = device
+
+
+_GEOM = {}  # handle value -> Geometry
+
+
+def check_tensor(t, where, name, dtype, numel, device=None, require_cuda=True):
+    """Raise HwenouError(EINVAL) unless `t` is a contiguous tensor of `dtype`
+    ('float64' / 'float32') with at least `numel` elements, on the GPU (and
+    on device index `device`, if given)."""
+    def bad(why):
+        raise HwenouError(HWENOU_EINVAL, where, f"{name}: {why}")
+    if not hasattr(t, "data_ptr") or not hasattr(t, "is_contiguous"):
+        bad("not a tensor")
+    if require_cuda and not t.is_cuda:
+        bad("not a GPU tensor")
+    if require_cuda and device is not None and t.device.index != device:
+        bad(f"on device {t.device.index}, the handle is on device {device}")
+    if str(t.dtype) != f"torch.{dtype}":
+        bad(f"dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        bad("not contiguous")
+    if t.numel() < numel:
+        bad(f"{t.numel()} elements, the handle's layout needs {numel}")
+
+
+def _geom(h, where):
+    g = _GEOM.get(getattr(h, "value", h))
+    if g is None:
+        raise HwenouError(HWENOU_EINVAL, where, "unknown or destroyed handle")
+    return g
+
+
+def _check_state(g, where, ubar, mom, names=("ubar", "mom")):
+    check_tensor(ubar, where, names[0], "float64", g.ncomp * g.plane, g.device)
+    check_tensor(mom, where, names[1], g.mom_dtype, g.dim * g.ncomp * g.plane, g.device)
 
 
 def make_desc(dim, eq, precision="fp64", char_decomp=True, weights="scale_invariant",
@@ -140,38 +198,72 @@ def make_inst(nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), bc="periodic", offset=0):
 def hwenou_create(desc, instances, stream=None):
     arr = (Inst * len(instances))(*instances)
     h = C.c_void_p()
+    import torch
     if stream is None:
-        import torch
         stream = torch.cuda.current_stream().cuda_stream
     _check(lib().hwenou_create(C.byref(desc), len(instances), arr, C.c_void_p(stream),
                                C.byref(h)), "hwenou_create")
+    _GEOM[h.value] = Geometry(desc, instances, torch.cuda.current_device())
     return h
 
 
 def hwenou_destroy(h):
+    _GEOM.pop(getattr(h, "value", h), None)
     _check(lib().hwenou_destroy(h), "hwenou_destroy")
 
 
 def hwenou_max_wavespeed(h, ubar, alpha):
-    _check(lib().hwenou_max_wavespeed(h, _ptr(ubar), _ptr(alpha)), "hwenou_max_wavespeed")
+    where = "hwenou_max_wavespeed"
+    g = _geom(h, where)
+    check_tensor(ubar, where, "ubar", "float64", g.ncomp * g.plane, g.device)
+    check_tensor(alpha, where, "alpha", "float64", 2 * g.n_inst, g.device)
+    _check(lib().hwenou_max_wavespeed(h, _ptr(ubar), _ptr(alpha)), where)
 
 
 def hwenou_stage(h, s, dt, alpha, ubar_in, mom_in, ubar_out, mom_out):
+    where = "hwenou_stage"
+    g = _geom(h, where)
+    check_tensor(dt, where, "dt", "float64", g.n_inst, g.device)
+    check_tensor(alpha, where, "alpha", "float64", 2 * g.n_inst, g.device)
+    _check_state(g, where, ubar_in, mom_in, ("ubar_in", "mom_in"))
+    _check_state(g, where, ubar_out, mom_out, ("ubar_out", "mom_out"))
     _check(lib().hwenou_stage(h, int(s), _ptr(dt), _ptr(alpha), _ptr(ubar_in), _ptr(mom_in),
-                              _ptr(ubar_out), _ptr(mom_out)), "hwenou_stage")
+                              _ptr(ubar_out), _ptr(mom_out)), where)
 
 
-def hwenou_advance(h, ubar, mom, cfl, t_final, max_steps, n_inst=1):
-    t = (C.c_double * n_inst)()
-    st = (C.c_int * n_inst)()
+def hwenou_advance(h, ubar, mom, cfl, t_final, max_steps):
+    """Returns (t, steps) per instance.  On ENONPHYSICAL the raised
+    NonPhysicalState carries them too (.t, .steps) and .flags, the
+    per-instance status."""
+    where = "hwenou_advance"
+    g = _geom(h, where)
+    _check_state(g, where, ubar, mom)
+    n = g.n_inst
+    t = (C.c_double * n)()
+    st = (C.c_int * n)()
     rc = lib().hwenou_advance(h, _ptr(ubar), _ptr(mom), float(cfl), float(t_final),
                               int(max_steps), t, st)
-    _check(rc, "hwenou_advance")
+    if rc == HWENOU_ENONPHYSICAL:
+        e = NonPhysicalState(rc, where)
+        e.t, e.steps = list(t), list(st)
+        e.flags = hwenou_inst_status(h)
+        raise e
+    _check(rc, where)
     return list(t), list(st)
 
 
 def hwenou_status(h):
     return lib().hwenou_status(h)
+
+
+def hwenou_inst_status(h):
+    """Per-instance flags (1 = left the physical states), read and cleared."""
+    g = _geom(h, "hwenou_inst_status")
+    flags = (C.c_int * g.n_inst)()
+    rc = lib().hwenou_inst_status(h, flags)
+    if rc not in (HWENOU_OK, HWENOU_ENONPHYSICAL):
+        _check(rc, "hwenou_inst_status")
+    return list(flags)
 
 
 def hwenou_set_launch(h, waves_per_cu, rows_per_item=0):
@@ -180,9 +272,11 @@ def hwenou_set_launch(h, waves_per_cu, rows_per_item=0):
 
 
 def hwenou_autotune(h, ubar, mom, reps=3):
+    where = "hwenou_autotune"
+    _check_state(_geom(h, where), where, ubar, mom)
     w, r = C.c_int(), C.c_int()
     _check(lib().hwenou_autotune(h, _ptr(ubar), _ptr(mom), int(reps), C.byref(w), C.byref(r)),
-           "hwenou_autotune")
+           where)
     return w.value, r.value
 
 
@@ -228,7 +322,10 @@ class Solver:
         hwenou_stage(self.h, s, dt, alpha, ubar_in, mom_in, ubar_out, mom_out)
 
     def advance(self, ubar, mom, cfl, t_final, max_steps):
-        return hwenou_advance(self.h, ubar, mom, cfl, t_final, max_steps, self.n_inst)
+        return hwenou_advance(self.h, ubar, mom, cfl, t_final, max_steps)
+
+    def inst_status(self):
+        return hwenou_inst_status(self.h)
 
     def set_launch(self, waves_per_cu, rows_per_item=0):
         hwenou_set_launch(self.h, waves_per_cu, rows_per_item)

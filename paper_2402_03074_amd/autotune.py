@@ -2,10 +2,12 @@
 
 The library's hwenou_autotune times the persistent stage launch for
 candidate waves per compute unit and (2D) rows per work item.  This module
-keys the winner by device architecture, scheme (dim, equation, precision,
-characteristic decomposition), the total cell count rounded to a power of two
-and the instance count rounded likewise, and stores it in a JSON file, so
-later handles of the same class reuse it without timing.
+keys the winner by device architecture and compute-unit count, scheme (dim,
+equation, precision, characteristic decomposition, and whether the weights
+are the scale-invariant ones, which are compiled into kernels of their own),
+the total cell count rounded to a power of two and the instance count
+rounded likewise, and stores it in a JSON file, so later handles of the same
+class reuse it without timing.
 
 Cache file: $HWENOU_TUNE_CACHE, else ~/.cache/hwenou/autotune.json.
 """
@@ -24,10 +26,13 @@ def cache_path():
 
 def _key(solver):
     import torch
-    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = props.gcnArchName.split(":")[0]
     d = solver.desc
     cells = max(1, int(solver.plane))
-    return "|".join(str(x) for x in (arch, d.dim, d.eq, d.precision, d.char_decomp,
+    scale_invariant = int(d.weights == 0)
+    return "|".join(str(x) for x in (arch, props.multi_processor_count, d.dim, d.eq,
+                                      d.precision, d.char_decomp, scale_invariant,
                                       int(math.log2(cells)),
                                       int(math.log2(max(1, solver.n_inst)))))
 

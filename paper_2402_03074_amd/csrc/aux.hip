@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void max_wavespeed_kernel(const AuxArgs A) {
     mx = fmax(mx, sx);
     my = fmax(my, sy);
   }
-  if (!ok) atomicOr(A.status, 1);
+  if (!ok) atomicOr(&A.status[inst], 1);
   mx = wave_max(mx);
   my = wave_max(my);
   if ((threadIdx.x & 63) == 0) {
@@ -57,32 +57,37 @@ hipError_t launch_max_wavespeed(const AuxArgs& a, hipStream_t s) {
 
 // Time step of instance k for the step that starts at its current t, from
 // its current alpha; marks the instance done when it has reached t_final or
-// max_steps (dt = 0 then).
+// max_steps, or when a kernel has flagged one of its states as non-physical
+// or non-finite (dt = 0 then: the instance stops at the step that failed,
+// and its t and step count say where).  The wave speeds are reduced with
+// fmax, which drops NaN arguments, so a NaN state is caught by the flag, not
+// by alpha.
 __device__ void set_step(const AuxArgs& A, int k) {
   const InstDev I = A.inst[k];
   const double t = A.t[k];
-  const bool finished = A.done[k] || A.steps[k] >= A.max_steps ||
-                        t >= A.t_final * (1.0 - 1e-14);
-  if (finished) {
+  const RunParams R = *A.run;
+  const bool finished = A.done[k] || A.steps[k] >= R.max_steps ||
+                        t >= R.t_final * (1.0 - 1e-14);
+  if (finished || A.status[k]) {
     A.done[k] = 1;
     A.dt[k] = 0.0;
     return;
   }
   const double ax = A.alpha[2 * k], ay = A.dim == 1 ? 0.0 : A.alpha[2 * k + 1];
-  if (!isfinite(ax) || !isfinite(ay)) {  // non-finite state: stop and report it
+  if (!isfinite(ax) || !isfinite(ay)) {  // infinite wave speed: stop and report it
     A.done[k] = 1;
     A.dt[k] = 0.0;
-    atomicOr(A.status, 1);
+    atomicOr(&A.status[k], 1);
     return;
   }
   double dt;
   if (ax == 0.0 && ay == 0.0)
-    dt = A.t_final - t;  // zero wave speed: every flux vanishes, the CFL bound is infinite
+    dt = R.t_final - t;  // zero wave speed: every flux vanishes, the CFL bound is infinite
   else if (A.dim == 1)
-    dt = A.cfl * I.dx / ax;
+    dt = R.cfl * I.dx / ax;
   else
-    dt = A.cfl / (ax / I.dx + ay / I.dy);
-  if (t + dt > A.t_final) dt = A.t_final - t;
+    dt = R.cfl / (ax / I.dx + ay / I.dy);
+  if (t + dt > R.t_final) dt = R.t_final - t;
   A.dt[k] = dt;
 }
 

@@ -47,7 +47,15 @@ struct hwenou_handle {
   // per-instance device state
   double *d_alpha = nullptr, *d_alpha_next = nullptr, *d_dt = nullptr, *d_t = nullptr;
   int *d_steps = nullptr, *d_done = nullptr, *d_status = nullptr, *d_all_done = nullptr;
-  int* h_all_done = nullptr;         // pinned
+  int* h_flags = nullptr;            // pinned [2]: all-done flags of the last two chunks
+  RunParams* d_run = nullptr;        // parameters of the current hwenou_advance call
+  RunParams* h_run = nullptr;        // pinned staging copy
+  hipEvent_t ev_poll[2] = {nullptr, nullptr};
+  // the step graph of hwenou_advance, kept while the state pointers and the
+  // work lists stay the same
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void *g_ubar = nullptr, *g_mom = nullptr;
   // scratch of the time loop and the stage base
   void* m_base = nullptr;            // v^_n (w^_n) [dim][nc][plane]
   double *s1u = nullptr, *s2u = nullptr;
@@ -82,16 +90,28 @@ int dalloc_bytes(void** p, size_t bytes) {
   return HWENOU_OK;
 }
 
+void drop_graph(hwenou_handle* h) {
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->exec = nullptr;
+  h->graph = nullptr;
+  h->g_ubar = h->g_mom = nullptr;
+}
+
 void free_handle(hwenou_handle* h) {
   if (!h) return;
+  drop_graph(h);
   auto f = [](void* p) {
     if (p) (void)hipFree(p);
   };
   f(h->d_inst); f(h->d_alpha); f(h->d_alpha_next); f(h->d_dt); f(h->d_t);
-  f(h->d_steps); f(h->d_done); f(h->d_status); f(h->d_all_done);
+  f(h->d_steps); f(h->d_done); f(h->d_status); f(h->d_all_done); f(h->d_run);
   f(h->m_base); f(h->s1u); f(h->s2u); f(h->s1m); f(h->s2m);
   f(h->d_work); f(h->d_work_ptr);
-  if (h->h_all_done) (void)hipHostFree(h->h_all_done);
+  if (h->h_flags) (void)hipHostFree(h->h_flags);
+  if (h->h_run) (void)hipHostFree(h->h_run);
+  for (hipEvent_t e : h->ev_poll)
+    if (e) (void)hipEventDestroy(e);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->ev_out) (void)hipEventDestroy(h->ev_out);
   if (h->own) (void)hipStreamDestroy(h->own);
@@ -105,6 +125,7 @@ void free_handle(hwenou_handle* h) {
 //      marches about the same number of rows (a run that crosses the end of
 //      a strip continues at the bottom of the next one).
 int build_work(hwenou_handle* h) {
+  drop_graph(h);  // the captured step graph holds the old work lists
   std::vector<WorkItem> items;
   std::vector<int> ptr;
   // default: as many waves per compute unit as can be resident at once
@@ -247,7 +268,7 @@ int launch_stage(hwenou_handle* h, int s, const double* dt, const double* alpha,
   return HWENOU_OK;
 }
 
-AuxArgs aux_args(hwenou_handle* h, const double* u, double cfl, double t_final, int max_steps) {
+AuxArgs aux_args(hwenou_handle* h, const double* u) {
   AuxArgs a;
   a.P = scheme_params(h->desc);
   a.eq = h->desc.eq;
@@ -263,9 +284,7 @@ AuxArgs aux_args(hwenou_handle* h, const double* u, double cfl, double t_final, 
   a.done = h->d_done;
   a.status = h->d_status;
   a.alpha_next = h->d_alpha_next;
-  a.cfl = cfl;
-  a.t_final = t_final;
-  a.max_steps = max_steps;
+  a.run = h->d_run;
   a.all_done = h->d_all_done;
   return a;
 }
@@ -373,8 +392,9 @@ int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, voi
   TRY(dalloc(&h->d_t, n_inst));
   TRY(dalloc(&h->d_steps, n_inst));
   TRY(dalloc(&h->d_done, n_inst));
-  TRY(dalloc(&h->d_status, 1));
+  TRY(dalloc(&h->d_status, n_inst));
   TRY(dalloc(&h->d_all_done, 1));
+  TRY(dalloc(&h->d_run, 1));
   TRY(dalloc_bytes(&h->m_base, mom_bytes));
   TRY(dalloc(&h->s1u, u_count));
   TRY(dalloc(&h->s2u, u_count));
@@ -388,10 +408,13 @@ int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, voi
     }
     return true;
   };
-  if (!chk(hipHostMalloc(reinterpret_cast<void**>(&h->h_all_done), sizeof(int)), "hipHostMalloc") ||
+  if (!chk(hipHostMalloc(reinterpret_cast<void**>(&h->h_flags), 2 * sizeof(int)), "hipHostMalloc") ||
+      !chk(hipHostMalloc(reinterpret_cast<void**>(&h->h_run), sizeof(RunParams)), "hipHostMalloc") ||
       !chk(hipMemcpy(h->d_inst, di.data(), n_inst * sizeof(InstDev), hipMemcpyHostToDevice),
            "hipMemcpy") ||
-      !chk(hipMemset(h->d_status, 0, sizeof(int)), "hipMemset") ||
+      !chk(hipMemset(h->d_status, 0, n_inst * sizeof(int)), "hipMemset") ||
+      !chk(hipEventCreateWithFlags(&h->ev_poll[0], hipEventDisableTiming), "hipEventCreate") ||
+      !chk(hipEventCreateWithFlags(&h->ev_poll[1], hipEventDisableTiming), "hipEventCreate") ||
       !chk(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking), "hipStreamCreate") ||
       !chk(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming), "hipEventCreate") ||
       !chk(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming), "hipEventCreate")) {
@@ -443,7 +466,7 @@ int hwenou_autotune(hwenou_handle* h, const double* ubar, const void* mom, int r
   HIPCHK(hipEventRecord(h->ev_in, h->stream));
   HIPCHK(hipStreamWaitEvent(st, h->ev_in, 0));
   HIPCHK(hipMemsetAsync(h->d_dt, 0, h->n_inst * sizeof(double), st));
-  AuxArgs a = aux_args(h, ubar, 1.0, 0.0, 0);
+  AuxArgs a = aux_args(h, ubar);
   hipError_t e = launch_max_wavespeed(a, st);
   if (e != hipSuccess) return hip_fail(e, "max_wavespeed launch");
   hipEvent_t t0, t1;
@@ -497,7 +520,7 @@ int hwenou_autotune(hwenou_handle* h, const double* ubar, const void* mom, int r
 int hwenou_max_wavespeed(hwenou_handle* h, const double* ubar, double* alpha_dev) {
   if (!h || !ubar || !alpha_dev || !aligned(ubar, 8) || !aligned(alpha_dev, 8))
     return HWENOU_EINVAL;
-  AuxArgs a = aux_args(h, ubar, 1.0, 0.0, 0);
+  AuxArgs a = aux_args(h, ubar);
   a.alpha = alpha_dev;
   hipError_t e = launch_max_wavespeed(a, h->stream);
   if (e != hipSuccess) return hip_fail(e, "max_wavespeed launch");
@@ -519,14 +542,22 @@ int hwenou_stage(hwenou_handle* h, int s, const double* dt_dev, const double* al
                       nullptr, h->stream);
 }
 
-int hwenou_status(hwenou_handle* h) {
+int hwenou_inst_status(hwenou_handle* h, int* flags) {
   if (!h) return HWENOU_EINVAL;
-  int st = 0;
+  std::vector<int> st(h->n_inst);
   HIPCHK(hipStreamSynchronize(h->stream));
-  HIPCHK(hipMemcpy(&st, h->d_status, sizeof(int), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemset(h->d_status, 0, sizeof(int)));
-  return (st & 1) ? HWENOU_ENONPHYSICAL : HWENOU_OK;
+  HIPCHK(hipStreamSynchronize(h->own));
+  HIPCHK(hipMemcpy(st.data(), h->d_status, h->n_inst * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemset(h->d_status, 0, h->n_inst * sizeof(int)));
+  int any = 0;
+  for (int k = 0; k < h->n_inst; ++k) {
+    if (flags) flags[k] = st[k] & 1;
+    any |= st[k] & 1;
+  }
+  return any ? HWENOU_ENONPHYSICAL : HWENOU_OK;
 }
+
+int hwenou_status(hwenou_handle* h) { return hwenou_inst_status(h, nullptr); }
 
 int hwenou_advance(hwenou_handle* h, double* ubar, void* mom, double cfl, double t_final,
                    int max_steps, double* t_out, int* steps_out) {
@@ -541,78 +572,97 @@ int hwenou_advance(hwenou_handle* h, double* ubar, void* mom, double cfl, double
   // order after the caller's prior work
   HIPCHK(hipEventRecord(h->ev_in, h->stream));
   HIPCHK(hipStreamWaitEvent(st, h->ev_in, 0));
+  // the previous call synchronised its stream, so the staging copy is free
+  h->h_run->cfl = cfl;
+  h->h_run->t_final = t_final;
+  h->h_run->max_steps = max_steps;
+  HIPCHK(hipMemcpyAsync(h->d_run, h->h_run, sizeof(RunParams), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(h->d_t, 0, h->n_inst * sizeof(double), st));
   HIPCHK(hipMemsetAsync(h->d_steps, 0, h->n_inst * sizeof(int), st));
   HIPCHK(hipMemsetAsync(h->d_done, 0, h->n_inst * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(h->d_status, 0, sizeof(int), st));
-  AuxArgs a = aux_args(h, ubar, cfl, t_final, max_steps);
+  HIPCHK(hipMemsetAsync(h->d_status, 0, h->n_inst * sizeof(int), st));
+  AuxArgs a = aux_args(h, ubar);
   hipError_t e = launch_max_wavespeed(a, st);
   if (e != hipSuccess) return hip_fail(e, "max_wavespeed launch");
   // the first step's dt; later ones are set by the finish kernel of the step before
   e = launch_dt(a, st);
   if (e != hipSuccess) return hip_fail(e, "dt launch");
 
-  // capture one step: three stages and the finish kernel
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  int rc = HWENOU_OK;
-  do {
-    rc = launch_stage(h, 0, h->d_dt, h->d_alpha, h->d_done, ubar, mom, h->s1u, h->s1m, nullptr, st);
-    if (rc) break;
-    h->u_base = ubar;
-    rc = launch_stage(h, 1, h->d_dt, h->d_alpha, h->d_done, h->s1u, h->s1m, h->s2u, h->s2m,
-                      nullptr, st);
-    if (rc) break;
-    rc = launch_stage(h, 2, h->d_dt, h->d_alpha, h->d_done, h->s2u, h->s2m, ubar, mom,
-                      h->d_alpha_next, st);
-    if (rc) break;
-    if ((e = launch_finish(a, st)) != hipSuccess) { rc = hip_fail(e, "finish launch"); break; }
-  } while (0);
-  e = hipStreamEndCapture(st, &graph);
-  if (rc) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return rc;
-  }
-  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return hip_fail(e, "hipGraphInstantiate");
-  }
-  const int chunk = 32;
-  int done_steps = 0;
-  const int limit = max_steps;
-  while (done_steps < limit) {
-    const int k = std::min(chunk, limit - done_steps);
-    for (int r = 0; r < k; ++r) {
-      e = hipGraphLaunch(exec, st);
-      if (e != hipSuccess) break;
+  // one step (three stages and the finish kernel) as a graph, captured once
+  // and replayed by every later call on the same state arrays
+  if (h->exec == nullptr || h->g_ubar != ubar || h->g_mom != mom) {
+    drop_graph(h);
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = HWENOU_OK;
+    do {
+      rc = launch_stage(h, 0, h->d_dt, h->d_alpha, h->d_done, ubar, mom, h->s1u, h->s1m, nullptr,
+                        st);
+      if (rc) break;
+      h->u_base = ubar;
+      rc = launch_stage(h, 1, h->d_dt, h->d_alpha, h->d_done, h->s1u, h->s1m, h->s2u, h->s2m,
+                        nullptr, st);
+      if (rc) break;
+      rc = launch_stage(h, 2, h->d_dt, h->d_alpha, h->d_done, h->s2u, h->s2m, ubar, mom,
+                        h->d_alpha_next, st);
+      if (rc) break;
+      if ((e = launch_finish(a, st)) != hipSuccess) {
+        rc = hip_fail(e, "finish launch");
+        break;
+      }
+    } while (0);
+    e = hipStreamEndCapture(st, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
     }
-    if (e != hipSuccess) break;
-    done_steps += k;
-    e = hipMemcpyAsync(h->h_all_done, h->d_all_done, sizeof(int), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) break;
-    if (*h->h_all_done) break;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&h->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      h->exec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    h->graph = graph;
+    h->g_ubar = ubar;
+    h->g_mom = mom;
   }
-  (void)hipGraphExecDestroy(exec);
-  (void)hipGraphDestroy(graph);
+  // Replays in chunks of growing length.  After each chunk the all-done flag
+  // is copied to a pinned slot; the host waits only for the flag of the chunk
+  // before, so the device never idles between chunks.  Steps replayed after
+  // every instance is done are no-ops.
+  int launched = 0, chunk = 8, slot = 0, prev = -1;
+  while (launched < max_steps && e == hipSuccess) {
+    const int k = std::min(chunk, max_steps - launched);
+    for (int r = 0; r < k && e == hipSuccess; ++r) e = hipGraphLaunch(h->exec, st);
+    if (e != hipSuccess) break;
+    launched += k;
+    e = hipMemcpyAsync(&h->h_flags[slot], h->d_all_done, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(h->ev_poll[slot], st);
+    if (e != hipSuccess) break;
+    if (prev >= 0) {
+      e = hipEventSynchronize(h->ev_poll[prev]);
+      if (e != hipSuccess || h->h_flags[prev]) break;
+    }
+    prev = slot;
+    slot ^= 1;
+    chunk = std::min(2 * chunk, 256);
+  }
   h->u_base = nullptr;  // the steps' stage-0 launches overwrote the stored v^n
   if (e != hipSuccess) return hip_fail(e, "graph replay");
   HIPCHK(hipStreamSynchronize(st));
   std::vector<double> t(h->n_inst);
-  std::vector<int> steps(h->n_inst);
-  int status = 0;
+  std::vector<int> steps(h->n_inst), status(h->n_inst);
   HIPCHK(hipMemcpy(t.data(), h->d_t, h->n_inst * sizeof(double), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(steps.data(), h->d_steps, h->n_inst * sizeof(int), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(&status, h->d_status, sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(status.data(), h->d_status, h->n_inst * sizeof(int), hipMemcpyDeviceToHost));
   if (t_out) std::memcpy(t_out, t.data(), h->n_inst * sizeof(double));
   if (steps_out) std::memcpy(steps_out, steps.data(), h->n_inst * sizeof(int));
   // later work on the caller's stream sees the result
   HIPCHK(hipEventRecord(h->ev_out, st));
   HIPCHK(hipStreamWaitEvent(h->stream, h->ev_out, 0));
-  if (status & 1) return HWENOU_ENONPHYSICAL;
+  for (int k = 0; k < h->n_inst; ++k)
+    if (status[k] & 1) return HWENOU_ENONPHYSICAL;
   return HWENOU_OK;
 }
 

@@ -154,9 +154,15 @@ __device__ __forceinline__ float rcp_nr(float x) {
 //   b_m = w_m - a g_m      (factor of p_m)
 // so that u_i = a p0 + sum_m b_m p_m.  Always evaluated in FP64.
 // SI = true compiles the scale-invariant weights alone (the default mode);
-// SI = false takes the weight mode from P at run time.
+// SI = false takes the weight mode from P at run time.  SCALE: scale the
+// denominators by a power of two before their products are formed (below);
+// on in the scale-invariant 2D kernels and in every 1D kernel.  The 2D
+// kernels that take the mode at run time (ZQ and linear weights) leave it
+// out to stay within their register budget: with u_ave = 1 their
+// denominators grow only like the square of the state, and the products stay
+// in range for states up to ~1e30.
 // ---------------------------------------------------------------------------
-template <int NM, bool SI, class TR>
+template <int NM, bool SI, class TR, bool SCALE = SI>
 __device__ __forceinline__ void combine_factors(const SchemeParams& P, const double (&beta)[NM + 1],
                                                 double u_ave, double& a, double (&b)[NM]) {
   // At run time the weight mode enters through exact arithmetic factors
@@ -169,20 +175,33 @@ __device__ __forceinline__ void combine_factors(const SchemeParams& P, const dou
 #pragma unroll
   for (int m = 1; m <= NM; ++m) t += fabs(beta[0] - beta[m]);
   t *= (1.0 / NM);
-  const double tau = t * t;
+  double tau = t * t;
   // unnormalised weights gamma_m e_m with e_m = 1 + tau / d_m and
   // d_m = beta_m u_ave + eps, all scaled by D = prod_k d_k so that one
   // reciprocal serves every weight: D e_m = D + tau P_m, with P_m the product
   // of the d_k other than d_m (prefix times suffix products).  The weights are
-  // ratios of these, so the scale cancels exactly.  d_m and tau scale like
-  // the fourth power of the reconstructed variable, so tau P_m like its
-  // (4 NM + 4)th: the products stay finite for variables below ~1e15 in
-  // magnitude (NM = 4; ~1e25 for NM = 2), and an eps of the paper's size
-  // keeps them from underflowing.  Beyond that range the weights come out non-finite (the
-  // per-field reciprocals of the plain form reach ~1e77).
+  // ratios of these, so the scale cancels exactly.  Before the products are
+  // formed, u_ave, eps and tau are scaled by 2^-E, with 2^E the binade of
+  // d_0, the quartic's denominator: the scaled d_0 lies in [1, 2) and the
+  // other d_m keep their ratios to it, so the products follow the spread of
+  // the d_m (wherever the data are not smooth d_0 is the largest; on smooth
+  // data all are of one size), not the magnitude of the state.  A power of
+  // two commutes with every rounding, so the scaled d_m and tau are exactly
+  // 2^-E times the unscaled ones and the weights are bitwise those of the
+  // unscaled form wherever that form stays in range.  What can still leave
+  // the range is a spread beyond ~1e70 between the d_m; the products of the
+  // smallest d_m then underflow, and those belong to the weights that are
+  // negligible.
+  double ua_s = u_ave, eps_s = P.eps;
+  if constexpr (SCALE) {
+    const int E = __builtin_amdgcn_frexp_exp(fma(beta[0], u_ave, P.eps)) - 1;
+    ua_s = ldexp(u_ave, -E);
+    eps_s = ldexp(P.eps, -E);
+    tau = ldexp(tau, -E);
+  }
   double d[NM + 1];
 #pragma unroll
-  for (int m = 0; m <= NM; ++m) d[m] = fma(beta[m], u_ave, P.eps);
+  for (int m = 0; m <= NM; ++m) d[m] = fma(beta[m], ua_s, eps_s);
   double pre[NM + 1], suf[NM + 1];  // pre[m] = d_0 .. d_{m-1}, suf[m] = d_m .. d_NM
   pre[1] = d[0];
 #pragma unroll
@@ -251,7 +270,7 @@ __device__ __forceinline__ void hweno_1d(const SchemeParams& P, const double (&c
   double beta[3] = {beta0_1d(c), s1 * s1, s2 * s2};
   const double ua = (aum + au0 + aup) * (1.0 / 3.0);
   double a, b[2];
-  combine_factors<2, false, TR>(P, beta, ua * ua, a, b);
+  combine_factors<2, false, TR, true>(P, beta, ua * ua, a, b);
   C[0] = (TR)(a * c[0] + (b[0] + b[1]) * u0);
   C[1] = (TR)(a * c[1] + b[0] * s1 + b[1] * s2);
   C[2] = (TR)(a * c[2]);

@@ -41,7 +41,7 @@ struct StageArgs {
   double* u_out;
   TM* m_out;
   double* alpha_next;   // [n_inst][2] or nullptr: max wave speed of the output
-  int* status;          // set to 1 on a non-physical or non-finite output
+  int* status;          // [n_inst]: set to 1 on a non-physical or non-finite output
   long long plane;      // cells per component plane
   const WorkItem* work;
   const int* work_ptr;  // wave w handles work[work_ptr[w] .. work_ptr[w+1])
@@ -62,6 +62,13 @@ hipError_t launch_stage_2d(int eq, int char_mode, bool mixed, bool scale_invaria
 int occupancy_stage_1d(int eq, int char_mode, bool mixed, int threads);
 int occupancy_stage_2d(int eq, int char_mode, bool mixed, bool scale_invariant, int threads);
 
+// Parameters of one hwenou_advance call, read by the time-step kernels from
+// device memory so that a captured step graph stays valid across calls.
+struct RunParams {
+  double cfl, t_final;
+  int max_steps;
+};
+
 // auxiliary kernels
 struct AuxArgs {
   SchemeParams P;
@@ -74,10 +81,9 @@ struct AuxArgs {
   double* t;             // [n_inst]
   int* steps;            // [n_inst]
   int* done;             // [n_inst]
-  int* status;
+  int* status;           // [n_inst]: 1 once the instance left the physical states
   double* alpha_next;    // [n_inst][2]
-  double cfl, t_final;
-  int max_steps;
+  const RunParams* run;  // CFL number, final time, step limit
   int* all_done;         // 1 when every instance is done
 };
 hipError_t launch_max_wavespeed(const AuxArgs& a, hipStream_t s);

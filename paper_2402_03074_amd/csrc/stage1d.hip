@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
       else
         ok = physical_state<EQ, NC>(Uo);
     }
-    if (!ok) atomicOr(A.status, 1);
+    if (!ok) atomicOr(&A.status[wk.inst], 1);
     if (ST == 2 && A.alpha_next != nullptr) {
       const double mx = wave_max(owner ? sx : 0.0);
       if (lane == 0) atomic_max_nonneg(&A.alpha_next[2 * wk.inst], mx);

@@ -205,8 +205,9 @@ __device__ __forceinline__ void char_field(const SchemeParams& P, const Prim& pr
 // so the fields are taken in the order 0, 3, 1, 2 and fold into S, D and
 // then into Cc.  The entropy field (K = 1) has the same left row and right
 // column in both directions: its polynomial is reconstructed once per cell
-// (by the first sweep) and passed to the second through LDS.
-template <int DIR, bool SI, class TR, class TM>
+// (by the first sweep) and passed to the second through LDS (PARK: a second
+// sweep follows).
+template <int DIR, bool SI, bool PARK, class TR, class TM>
 __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr,
                                            const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
                                            TR (&Cc)[4][15], TR (*c1buf)[64], bool have_c1) {
@@ -239,10 +240,11 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
     double a1;
     if (!have_c1) {
       char_field<DIR, 1, SI, TR, TM>(P, pr, B, sb, sc, st, l, C1, a1);
-      // parked in LDS for the other sweep
+      if constexpr (PARK) {  // parked in LDS for the other sweep
 #pragma unroll
-      for (int n = 0; n < 15; ++n) c1buf[n][l] = C1[n];
-      c1buf[15][l] = (TR)a1;
+        for (int n = 0; n < 15; ++n) c1buf[n][l] = C1[n];
+        c1buf[15][l] = (TR)a1;
+      }
     } else {
 #pragma unroll
       for (int n = 0; n < 15; ++n) C1[n] = c1buf[n][l];
@@ -438,7 +440,8 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
         pr = make_prim<TR>(gm1, U5);
-        char_sweep<SPLIT ? 1 : 0, SI, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, false);
+        char_sweep<SPLIT ? 1 : 0, SI, SPLIT, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf,
+                                                      false);
       } else {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
@@ -556,7 +559,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
       if (row_out) {
         // ---- x-direction reconstruction of row j ----
         if constexpr (SPLIT)
-          char_sweep<0, SI, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, true);
+          char_sweep<0, SI, false, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, true);
         double F1x[NC];
         TR F2x[NC], F3x[NC];
 #pragma unroll
@@ -620,7 +623,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
       sc = st;
       st = s0;
     }
-    if (!ok) atomicOr(A.status, 1);
+    if (!ok) atomicOr(&A.status[wk.inst], 1);
     if (ST == 2 && A.alpha_next != nullptr) {
       const double mx = wave_max(amax_x), my = wave_max(amax_y);
       if (lane == 0) {

@@ -91,3 +91,59 @@ def test_calls_reject_null_handle():
     assert L.hwenou_stage(None, 0, None, None, None, None, None, None) == H.HWENOU_EINVAL
     assert L.hwenou_advance(None, None, None, 0.5, 1.0, 1, None, None) == H.HWENOU_EINVAL
     assert L.hwenou_set_launch(None, 1, 0) == H.HWENOU_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# argument checks of the Python binding: bad tensors are rejected before the
+# C-ABI is called (nothing is launched; CPU tensors stand in for the cases
+# that need no device)
+# ---------------------------------------------------------------------------
+
+def _geom(dim=2, eq="euler", precision="fp64"):
+    d = H.make_desc(dim, eq, precision)
+    insts = [H.make_inst(8, 6 if dim == 2 else 1, (0, 1, 0, 1)),
+             H.make_inst(5, 4 if dim == 2 else 1, (0, 1, 0, 1), offset=48)]
+    return H.Geometry(d, insts)
+
+
+def test_geometry_of_a_handle():
+    g = _geom()
+    assert (g.dim, g.ncomp, g.n_inst, g.plane, g.mom_dtype) == (2, 4, 2, 68, "float64")
+    g = _geom(1, "advection", "mixed")
+    assert (g.dim, g.ncomp, g.plane, g.mom_dtype) == (1, 1, 53, "float32")
+
+
+@pytest.mark.parametrize("case", ["cpu", "dtype", "noncontig", "short", "not_tensor"])
+def test_binding_rejects_bad_tensors(case):
+    import torch
+    g = _geom()
+    need = g.dim * g.ncomp * g.plane
+    t = {"cpu": torch.zeros(need, dtype=torch.float64),
+         "dtype": torch.zeros(need, dtype=torch.float32),
+         "noncontig": torch.zeros(2 * need, dtype=torch.float64)[::2],
+         "short": torch.zeros(need - 1, dtype=torch.float64),
+         "not_tensor": [0.0] * need}[case]
+    with pytest.raises(H.HwenouError) as e:
+        H.check_tensor(t, "hwenou_stage", "mom_in", g.mom_dtype, need,
+                       require_cuda=(case == "cpu"))
+    assert e.value.code == H.HWENOU_EINVAL
+    assert "mom_in" in str(e.value)
+
+
+def test_binding_accepts_a_matching_tensor():
+    import torch
+    g = _geom(precision="mixed")
+    need = g.dim * g.ncomp * g.plane
+    H.check_tensor(torch.zeros(need, dtype=torch.float32), "w", "mom", g.mom_dtype, need,
+                   require_cuda=False)
+
+
+def test_binding_rejects_unknown_handles():
+    import torch
+    u = torch.zeros(4)
+    for call in (lambda: H.hwenou_stage(C.c_void_p(12345), 0, u, u, u, u, u, u),
+                 lambda: H.hwenou_advance(C.c_void_p(12345), u, u, 0.5, 1.0, 1),
+                 lambda: H.hwenou_max_wavespeed(C.c_void_p(12345), u, u)):
+        with pytest.raises(H.HwenouError) as e:
+            call()
+        assert e.value.code == H.HWENOU_EINVAL

@@ -347,6 +347,59 @@ def test_non_finite_state_is_reported():
     u0[0, 10] = np.nan
     S = solver_for(P)
     ug, mg = to_gpu(u0), to_gpu(m0)
-    with pytest.raises(H.NonPhysicalState):
+    with pytest.raises(H.NonPhysicalState) as e:
         S.advance(ug, mg, 0.6, 1e30, 3)
+    assert e.value.steps == [0] and e.value.t == [0.0] and e.value.flags == [1]
     S.close()
+
+
+def _vacuum_1d(n):
+    """Two streams leaving each other at Mach ~10: a vacuum forms and the
+    scheme (which has no positivity limiter) leaves the physical states
+    within a few steps (the oracle fails in its third step)."""
+    x = (np.arange(n) + 0.5) / n
+    rho = np.ones(n)
+    u = np.where(x < 0.5, -6.0, 6.0)
+    p = 0.2 * np.ones(n)
+    U = np.stack([rho, rho * u, p / 0.4 + 0.5 * rho * u * u])
+    return U, np.zeros((1, 3, n))
+
+
+@pytest.mark.parametrize("bad", ["nan", "vacuum"])
+def test_failed_instance_stops_alone(bad):
+    """Per-instance failure: the instance whose state leaves the physical
+    states stops after the step in which that happened (its t and step count
+    say where, its flag is set), while the other instances run every step
+    and equal runs of themselves alone, bitwise."""
+    print(f"[gpu] failed instance stops alone: {bad}", flush=True)
+    sizes = [64, 80, 48]
+    insts, u, m = _batch_1d(sizes, 7700)
+    if bad == "nan":
+        u[0, 64 + 10] = np.nan  # instance 1, before the first step
+    else:
+        uv, mv = _vacuum_1d(80)
+        u[:, 64:144] = uv
+        m[:, :, 64:144] = mv
+    S = H.Solver(1, "euler", insts)
+    ug, mg = to_gpu(u), to_gpu(m)
+    steps = 12
+    with pytest.raises(H.NonPhysicalState) as e:
+        S.advance(ug, mg, 0.6, 1e30, steps)
+    st, t, flags = e.value.steps, e.value.t, e.value.flags
+    assert flags == [0, 1, 0], flags
+    assert st[0] == st[2] == steps
+    if bad == "nan":
+        assert st[1] == 0 and t[1] == 0.0
+    else:
+        assert 1 <= st[1] < steps and 0.0 < t[1] < t[0], (st, t)
+    assert H.hwenou_inst_status(S.h) == [0, 0, 0]  # read and cleared
+    out = ug.cpu().numpy()
+    S.close()
+    for k, off in ((0, 0), (2, 144)):
+        n = sizes[k]
+        S1 = H.Solver(1, "euler", [H.make_inst(n, 1, (0.0, 1.0), "transmissive")])
+        u1, m1 = to_gpu(np.ascontiguousarray(u[:, off:off + n])), \
+            to_gpu(np.ascontiguousarray(m[:, :, off:off + n]))
+        S1.advance(u1, m1, 0.6, 1e30, steps)
+        assert np.array_equal(u1.cpu().numpy(), out[:, off:off + n]), k
+        S1.close()

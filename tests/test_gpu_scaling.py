@@ -11,9 +11,13 @@ every rounding commutes with the scaling, so one step with the state scaled
 by zeta and eps by zeta^4 must give exactly zeta times the unscaled step.
 
 The check is GPU against GPU (no oracle arithmetic).  It covers both
-precisions and both dimensions, and the state magnitudes the weights'
-product form is documented for: zeta = 2^40 puts the state near 1e13 and
-the products of the five 2D denominators near 1e240.
+precisions and both dimensions.  The weights are formed with one reciprocal
+over products of the denominators beta_m u_ave + eps, which are first scaled
+by a power of two so that the products do not follow the state's magnitude:
+zeta = 2^200 puts the unscaled products of the five 2D denominators far
+beyond the FP64 range (the state near 1e60, each denominator near 1e240).
+The mixed form stops at 2^60, where its FP32 point values and fluxes still
+stay clear of the FP32 overflow and subnormal ranges.
 """
 import numpy as np
 import pytest
@@ -36,8 +40,11 @@ def _case(dim):
     return Problem(2, "euler", (70, 64), (0, 10, 0, 10)), u, m
 
 
-@pytest.mark.parametrize("k", [-40, -20, 20, 40])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+CASES = ([("fp64", k) for k in (-200, -100, -40, -20, 20, 40, 100, 200)] +
+         [("mixed", k) for k in (-60, -40, -20, 20, 40, 60)])
+
+
+@pytest.mark.parametrize("precision,k", CASES)
 @pytest.mark.parametrize("dim", [1, 2])
 def test_stage_is_homogeneous_under_power_of_two_scaling(dim, precision, k):
     P, u, m = _case(dim)
