@@ -49,7 +49,8 @@ enum {
   HWENOU_ENOMEM = 2,        /* device allocation failed */
   HWENOU_EHIP = 3,          /* a HIP call failed */
   HWENOU_ENONPHYSICAL = 4,  /* rho <= 0, p <= 0 or non-finite value after a stage */
-  HWENOU_EUNSUPPORTED = 5
+  HWENOU_EUNSUPPORTED = 5,
+  HWENOU_ESCRATCH = 6       /* hwenou_step_noalloc: instance beyond its fixed scratch */
 };
 
 enum { HWENOU_EQ_ADVECTION = 0, HWENOU_EQ_BURGERS = 1, HWENOU_EQ_EULER = 2 };
@@ -191,6 +192,33 @@ int hwenou_set_launch(hwenou_handle* h, int waves_per_cu, int rows_per_item);
  * Synchronous.  Errors: EINVAL, EHIP. */
 int hwenou_autotune(hwenou_handle* h, const double* ubar, const void* mom, int reps,
                     int* waves_per_cu, int* rows_per_item);
+
+/* Size of the fixed device scratch of hwenou_step_noalloc: 64 MiB per device
+ * (held from the first call on a device until the process ends). */
+#define HWENOU_NOALLOC_MAX_BYTES 67108864
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One whole
+ * step of the modified SSP-RK3 (Eq. (2.13)), the three stages of
+ * hwenou_stage in order, of ONE instance (inst->offset must be 0), in place
+ * on the caller's (ubar, mom), with the caller's device values dt_dev [1] and
+ * alpha_dev [2]; no handle.  Every scratch buffer (the stored modified
+ * moments, two stage buffers, the instance record and the work lists) lives
+ * in one fixed device array of HWENOU_NOALLOC_MAX_BYTES per device, so the
+ * call allocates nothing: about 256 bytes per cell for 2D Euler in FP64
+ * (~250k cells, 500^2), 120 for 1D Euler.  Every call on a device shares that
+ * array and rebuilds what it reads from it, so calls that overlap on one
+ * device (other streams or threads) race: order them.  The first call on a
+ * device looks up the array's address there (make it outside graph capture).
+ * status_dev (device int, may be NULL) is OR-ed with 1 if a stage finds a
+ * non-physical or non-finite state; it is not cleared.  Asynchronous on
+ * `stream` (a hipStream_t, NULL = default).  Results equal those of
+ * hwenou_stage with the same dt and alpha.  Errors: EINVAL (description,
+ * instance, offset or a misaligned pointer), EUNSUPPORTED, ESCRATCH (the
+ * instance does not fit the array), EHIP. */
+int hwenou_step_noalloc(const hwenou_desc* desc, const hwenou_inst* inst, void* stream,
+                        const double* dt_dev, const double* alpha_dev, double* ubar, void* mom,
+                        int* status_dev);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhwenou.so")
 
 HWENOU_OK, HWENOU_EINVAL, HWENOU_ENOMEM, HWENOU_EHIP, HWENOU_ENONPHYSICAL, \
-    HWENOU_EUNSUPPORTED = range(6)
+    HWENOU_EUNSUPPORTED, HWENOU_ESCRATCH = range(7)
+HWENOU_NOALLOC_MAX_BYTES = 64 << 20
 EQ = {"advection": 0, "burgers": 1, "euler": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 WEIGHTS = {"scale_invariant": 0, "zq": 1, "linear": 2}
@@ -38,7 +39,7 @@ CHAR = {"component": 0, "split": 1, "single": 2}
 
 EXPORTS = ["hwenou_create", "hwenou_destroy", "hwenou_strerror", "hwenou_max_wavespeed",
            "hwenou_stage", "hwenou_advance", "hwenou_status", "hwenou_inst_status",
-           "hwenou_set_launch", "hwenou_autotune"]
+           "hwenou_set_launch", "hwenou_autotune", "hwenou_step_noalloc"]
 
 
 class HwenouError(RuntimeError):
@@ -89,6 +90,7 @@ def lib():
     L.hwenou_inst_status.argtypes = [vp, C.POINTER(C.c_int)]
     L.hwenou_set_launch.argtypes = [vp, C.c_int, C.c_int]
     L.hwenou_autotune.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.hwenou_step_noalloc.argtypes = [C.POINTER(Desc), C.POINTER(Inst), vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = C.c_char_p if name == "hwenou_strerror" else C.c_int
     _lib = L
@@ -278,6 +280,24 @@ def hwenou_autotune(h, ubar, mom, reps=3):
     _check(lib().hwenou_autotune(h, _ptr(ubar), _ptr(mom), int(reps), C.byref(w), C.byref(r)),
            where)
     return w.value, r.value
+
+
+def hwenou_step_noalloc(desc, inst, dt, alpha, ubar, mom, status=None, stream=None):
+    """One Runge-Kutta step of one instance in place, with no device
+    allocation (fixed device scratch of the library); see include/hwenou.h."""
+    import torch
+    where = "hwenou_step_noalloc"
+    g = Geometry(desc, [inst], torch.cuda.current_device())
+    check_tensor(dt, where, "dt", "float64", 1, g.device)
+    check_tensor(alpha, where, "alpha", "float64", 2, g.device)
+    _check_state(g, where, ubar, mom)
+    if status is not None:
+        check_tensor(status, where, "status", "int32", 1, g.device)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(lib().hwenou_step_noalloc(C.byref(desc), C.byref(inst), C.c_void_p(stream),
+                                     _ptr(dt), _ptr(alpha), _ptr(ubar), _ptr(mom),
+                                     _ptr(status) if status is not None else None), where)
 
 
 class Solver:

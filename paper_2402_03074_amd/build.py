@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhwenou.so")
-SOURCES = ["hwenou_api.hip", "stage1d.hip", "stage2d.hip", "aux.hip"]
+SOURCES = ["hwenou_api.hip", "stage1d.hip", "stage2d.hip", "aux.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HWENOU_ARCH", "gfx950")
 

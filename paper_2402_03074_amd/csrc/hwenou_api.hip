@@ -201,7 +201,9 @@ int build_work(hwenou_handle* h) {
   return HWENOU_OK;
 }
 
-SchemeParams scheme_params(const hwenou_desc& d) {
+}  // namespace
+
+SchemeParams hwenou::scheme_params(const hwenou_desc& d) {
   SchemeParams P;
   P.adv_x = d.adv[0];
   P.adv_y = d.adv[1];
@@ -213,6 +215,8 @@ SchemeParams scheme_params(const hwenou_desc& d) {
   P.nonlin = d.weights == HWENOU_W_LINEAR ? 0.0 : 1.0;
   return P;
 }
+
+namespace {
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -291,6 +295,49 @@ AuxArgs aux_args(hwenou_handle* h, const double* u) {
 
 }  // namespace
 
+namespace hwenou {
+
+int check_desc(const hwenou_desc* d) {
+  if (!d) return HWENOU_EINVAL;
+  if (d->dim != 1 && d->dim != 2) return HWENOU_EINVAL;
+  if (d->eq < HWENOU_EQ_ADVECTION || d->eq > HWENOU_EQ_EULER) return HWENOU_EINVAL;
+  if (d->precision != HWENOU_FP64 && d->precision != HWENOU_MIXED) return HWENOU_EINVAL;
+  if (d->weights < HWENOU_W_SCALE_INVARIANT || d->weights > HWENOU_W_LINEAR) return HWENOU_EINVAL;
+  if (d->char_decomp < HWENOU_CHAR_COMPONENT || d->char_decomp > HWENOU_CHAR_SINGLE)
+    return HWENOU_EINVAL;
+  if (!(d->gamma_low > 0.0) || d->gamma_low * (d->dim == 1 ? 2 : 4) >= 1.0) return HWENOU_EINVAL;
+  if (!(d->eps >= 0.0)) return HWENOU_EINVAL;
+  if (d->eq == HWENOU_EQ_EULER && !(d->gas_gamma > 1.0)) return HWENOU_EINVAL;
+  return HWENOU_OK;
+}
+
+int check_inst(const hwenou_desc* d, const hwenou_inst& I) {
+  const int ny = d->dim == 1 ? 1 : I.ny;
+  if (I.nx < 3 || (d->dim == 2 && ny < 3)) return HWENOU_EINVAL;
+  if (!(I.x1 > I.x0) || (d->dim == 2 && !(I.y1 > I.y0))) return HWENOU_EINVAL;
+  for (int s = 0; s < 2 * d->dim; ++s)
+    if (I.bc[s] != HWENOU_BC_PERIODIC && I.bc[s] != HWENOU_BC_TRANSMISSIVE &&
+        !(I.bc[s] == HWENOU_BC_REFLECTIVE && d->eq == HWENOU_EQ_EULER))
+      return HWENOU_EINVAL;
+  if (I.offset < 0) return HWENOU_EINVAL;
+  const long long n = (long long)I.nx * ny;
+  if (n > (1LL << 29)) return HWENOU_EUNSUPPORTED;  // 32-bit byte offsets in the kernels
+  return HWENOU_OK;
+}
+
+InstDev inst_dev(const hwenou_desc* d, const hwenou_inst& I) {
+  InstDev r;
+  r.nx = I.nx;
+  r.ny = d->dim == 1 ? 1 : I.ny;
+  for (int s = 0; s < 4; ++s) r.bc[s] = (s < 2 * d->dim) ? I.bc[s] : HWENOU_BC_PERIODIC;
+  r.dx = (I.x1 - I.x0) / I.nx;
+  r.dy = d->dim == 1 ? 1.0 : (I.y1 - I.y0) / I.ny;
+  r.offset = I.offset;
+  return r;
+}
+
+}  // namespace hwenou
+
 extern "C" {
 
 const char* hwenou_strerror(int code) {
@@ -301,39 +348,28 @@ const char* hwenou_strerror(int code) {
     case HWENOU_EHIP: return g_hip_error[0] ? g_hip_error : "HIP error";
     case HWENOU_ENONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
     case HWENOU_EUNSUPPORTED: return "unsupported configuration";
+    case HWENOU_ESCRATCH:
+      return "instance too large for the fixed scratch of hwenou_step_noalloc "
+             "(HWENOU_NOALLOC_MAX_BYTES)";
     default: return "unknown error code";
   }
 }
+
 
 int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, void* stream,
                   hwenou_handle** out) {
   if (!out) return HWENOU_EINVAL;
   *out = nullptr;
   if (!d || !inst || n_inst < 1) return HWENOU_EINVAL;
-  if (d->dim != 1 && d->dim != 2) return HWENOU_EINVAL;
-  if (d->eq < HWENOU_EQ_ADVECTION || d->eq > HWENOU_EQ_EULER) return HWENOU_EINVAL;
-  if (d->precision != HWENOU_FP64 && d->precision != HWENOU_MIXED) return HWENOU_EINVAL;
-  if (d->weights < HWENOU_W_SCALE_INVARIANT || d->weights > HWENOU_W_LINEAR) return HWENOU_EINVAL;
-  if (d->char_decomp < HWENOU_CHAR_COMPONENT || d->char_decomp > HWENOU_CHAR_SINGLE)
-    return HWENOU_EINVAL;
-  if (!(d->gamma_low > 0.0) || d->gamma_low * (d->dim == 1 ? 2 : 4) >= 1.0) return HWENOU_EINVAL;
-  if (!(d->eps >= 0.0)) return HWENOU_EINVAL;
-  if (d->eq == HWENOU_EQ_EULER && !(d->gas_gamma > 1.0)) return HWENOU_EINVAL;
+  int rc0 = check_desc(d);
+  if (rc0) return rc0;
   // instances: sizes, domains, boundary conditions, non-overlapping ranges
   std::vector<std::pair<long long, long long>> ranges;
   long long plane = 0;
   for (int k = 0; k < n_inst; ++k) {
     const hwenou_inst& I = inst[k];
-    const int ny = d->dim == 1 ? 1 : I.ny;
-    if (I.nx < 3 || (d->dim == 2 && ny < 3)) return HWENOU_EINVAL;
-    if (!(I.x1 > I.x0) || (d->dim == 2 && !(I.y1 > I.y0))) return HWENOU_EINVAL;
-    for (int s = 0; s < 2 * d->dim; ++s)
-      if (I.bc[s] != HWENOU_BC_PERIODIC && I.bc[s] != HWENOU_BC_TRANSMISSIVE &&
-          !(I.bc[s] == HWENOU_BC_REFLECTIVE && d->eq == HWENOU_EQ_EULER))
-        return HWENOU_EINVAL;
-    if (I.offset < 0) return HWENOU_EINVAL;
-    const long long n = (long long)I.nx * ny;
-    if (n > (1LL << 29)) return HWENOU_EUNSUPPORTED;  // 32-bit byte offsets in the kernels
+    if ((rc0 = check_inst(d, I))) return rc0;
+    const long long n = (long long)I.nx * (d->dim == 1 ? 1 : I.ny);
     ranges.push_back({I.offset, I.offset + n});
     plane = std::max(plane, (long long)(I.offset + n));
   }
@@ -366,15 +402,7 @@ int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, voi
   h->n_cu = prop.multiProcessorCount;
 
   std::vector<InstDev> di(n_inst);
-  for (int k = 0; k < n_inst; ++k) {
-    const hwenou_inst& I = inst[k];
-    di[k].nx = I.nx;
-    di[k].ny = d->dim == 1 ? 1 : I.ny;
-    for (int s = 0; s < 4; ++s) di[k].bc[s] = (s < 2 * d->dim) ? I.bc[s] : HWENOU_BC_PERIODIC;
-    di[k].dx = (I.x1 - I.x0) / I.nx;
-    di[k].dy = d->dim == 1 ? 1.0 : (I.y1 - I.y0) / I.ny;
-    di[k].offset = I.offset;
-  }
+  for (int k = 0; k < n_inst; ++k) di[k] = inst_dev(d, inst[k]);
   const size_t mom_bytes = (size_t)h->dim * h->nc * plane * h->mom_elem;
   const size_t u_count = (size_t)h->nc * plane;
 #define TRY(x)            \

@@ -49,6 +49,16 @@ struct StageArgs {
   int stage;            // 0, 1, 2
 };
 
+// Host helpers shared by the entry points (hwenou_api.hip).
+}  // namespace hwenou
+struct hwenou_desc;
+struct hwenou_inst;
+namespace hwenou {
+int check_desc(const hwenou_desc* d);                           // HWENOU_OK or an error code
+int check_inst(const hwenou_desc* d, const hwenou_inst& inst);  // one instance's own checks
+InstDev inst_dev(const hwenou_desc* d, const hwenou_inst& inst);
+SchemeParams scheme_params(const hwenou_desc& d);
+
 // kernel launchers (one per translation unit); return hipSuccess or the launch error.
 // char_mode (Euler): 0 component-wise, 1 direction-split characteristic, 2 single
 // x-projection (the same as 1 in 1D)

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_strerror_codes():
-    for code in range(6):
+    for code in range(7):
         assert isinstance(H.strerror(code), str) and H.strerror(code)
     assert "non-physical" in H.strerror(H.HWENOU_ENONPHYSICAL)
 
@@ -147,3 +147,21 @@ def test_binding_rejects_unknown_handles():
         with pytest.raises(H.HwenouError) as e:
             call()
         assert e.value.code == H.HWENOU_EINVAL
+
+
+def test_no_alloc_step_rejects_bad_arguments_without_a_device():
+    L = H.lib()
+    d = H.make_desc(2, "euler")
+    i = H.make_inst(10, 10, (0, 1, 0, 1))
+    assert L.hwenou_step_noalloc(None, None, None, None, None, None, None, None) == \
+        H.HWENOU_EINVAL
+    assert L.hwenou_step_noalloc(C.byref(d), C.byref(i), None, None, None, None, None,
+                                 None) == H.HWENOU_EINVAL
+    bad = H.make_desc(2, "euler")
+    bad.dim = 3
+    one = C.c_void_p(256)  # never dereferenced: the description is rejected first
+    assert L.hwenou_step_noalloc(C.byref(bad), C.byref(i), None, one, one, one, one,
+                                 None) == H.HWENOU_EINVAL
+    off = H.make_inst(10, 10, (0, 1, 0, 1), offset=5)  # one instance, at offset 0 only
+    assert L.hwenou_step_noalloc(C.byref(d), C.byref(off), None, one, one, one, one,
+                                 None) == H.HWENOU_EINVAL
