@@ -16,8 +16,10 @@ over products of the denominators beta_m u_ave + eps, which are first scaled
 by a power of two so that the products do not follow the state's magnitude:
 zeta = 2^200 puts the unscaled products of the five 2D denominators far
 beyond the FP64 range (the state near 1e60, each denominator near 1e240).
-The mixed form stops at 2^60, where its FP32 point values and fluxes still
-stay clear of the FP32 overflow and subnormal ranges.
+The mixed form goes up to 2^60, where its FP32 point values and fluxes stay
+clear of the FP32 overflow range, and down to 2^-40: at 2^-60 products of
+small FP32 moment terms of the 2D form reach the subnormal range, where a
+power of two no longer scales them exactly.
 """
 import numpy as np
 import pytest
@@ -41,7 +43,7 @@ def _case(dim):
 
 
 CASES = ([("fp64", k) for k in (-200, -100, -40, -20, 20, 40, 100, 200)] +
-         [("mixed", k) for k in (-60, -40, -20, 20, 40, 60)])
+         [("mixed", k) for k in (-40, -20, 20, 40, 60)])
 
 
 @pytest.mark.parametrize("precision,k", CASES)
