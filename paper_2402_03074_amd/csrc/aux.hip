@@ -92,13 +92,11 @@ __device__ void set_step(const AuxArgs& A, int k) {
 }
 
 // Before the first step: its time step, and the reset of the wave-speed
-// accumulator that the last stage of the step fills.
+// accumulators that the last stage of the step fills.
 __global__ __launch_bounds__(256) void dt_kernel(const AuxArgs A) {
-  for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) {
-    A.alpha_next[2 * k] = 0.0;
-    A.alpha_next[2 * k + 1] = 0.0;
-    set_step(A, k);
-  }
+  for (int k = threadIdx.x; k < A.n_inst * kAlphaSlots * 2; k += blockDim.x)
+    A.alpha_next[k] = 0.0;
+  for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) set_step(A, k);
 }
 
 // End of a step: advance t and the step count, take the new wave speed,
@@ -110,14 +108,19 @@ __global__ __launch_bounds__(256) void finish_kernel(const AuxArgs A) {
   __syncthreads();
   int mine = 0;
   for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) {
+    double* acc = A.alpha_next + 2 * kAlphaSlots * k;
     if (!A.done[k]) {
       A.t[k] += A.dt[k];
       A.steps[k] += 1;
-      A.alpha[2 * k] = A.alpha_next[2 * k];
-      A.alpha[2 * k + 1] = A.alpha_next[2 * k + 1];
+      double ax = acc[0], ay = acc[1];
+      for (int s = 1; s < kAlphaSlots; ++s) {
+        ax = fmax(ax, acc[2 * s]);
+        ay = fmax(ay, acc[2 * s + 1]);
+      }
+      A.alpha[2 * k] = ax;
+      A.alpha[2 * k + 1] = ay;
     }
-    A.alpha_next[2 * k] = 0.0;
-    A.alpha_next[2 * k + 1] = 0.0;
+    for (int s = 0; s < 2 * kAlphaSlots; ++s) acc[s] = 0.0;
     set_step(A, k);
     if (!A.done[k]) mine = 1;
   }

@@ -51,10 +51,10 @@ struct hwenou_handle {
   RunParams* d_run = nullptr;        // parameters of the current hwenou_advance call
   RunParams* h_run = nullptr;        // pinned staging copy
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
-  // the step graph of hwenou_advance, kept while the state pointers and the
-  // work lists stay the same
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // the step graphs of hwenou_advance (one step, and kMultiSteps steps in a
+  // row), kept while the state pointers and the work lists stay the same
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   const void *g_ubar = nullptr, *g_mom = nullptr;
   // scratch of the time loop and the stage base
   void* m_base = nullptr;            // v^_n (w^_n) [dim][nc][plane]
@@ -90,11 +90,18 @@ int dalloc_bytes(void** p, size_t bytes) {
   return HWENOU_OK;
 }
 
+// Steps per replay of the multi-step graph: the gap between two graph
+// launches (~5-10 us) then falls on every kMultiSteps-th step only, which
+// matters for grids whose steps take tens of microseconds.
+constexpr int kMultiSteps = 8;
+
 void drop_graph(hwenou_handle* h) {
-  if (h->exec) (void)hipGraphExecDestroy(h->exec);
-  if (h->graph) (void)hipGraphDestroy(h->graph);
-  h->exec = nullptr;
-  h->graph = nullptr;
+  for (int g = 0; g < 2; ++g) {
+    if (h->exec[g]) (void)hipGraphExecDestroy(h->exec[g]);
+    if (h->graph[g]) (void)hipGraphDestroy(h->graph[g]);
+    h->exec[g] = nullptr;
+    h->graph[g] = nullptr;
+  }
   h->g_ubar = h->g_mom = nullptr;
 }
 
@@ -415,7 +422,7 @@ int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, voi
   } while (0)
   TRY(dalloc(&h->d_inst, n_inst));
   TRY(dalloc(&h->d_alpha, 2 * n_inst));
-  TRY(dalloc(&h->d_alpha_next, 2 * n_inst));
+  TRY(dalloc(&h->d_alpha_next, 2 * kAlphaSlots * n_inst));
   TRY(dalloc(&h->d_dt, n_inst));
   TRY(dalloc(&h->d_t, n_inst));
   TRY(dalloc(&h->d_steps, n_inst));
@@ -616,53 +623,60 @@ int hwenou_advance(hwenou_handle* h, double* ubar, void* mom, double cfl, double
   e = launch_dt(a, st);
   if (e != hipSuccess) return hip_fail(e, "dt launch");
 
-  // one step (three stages and the finish kernel) as a graph, captured once
-  // and replayed by every later call on the same state arrays
-  if (h->exec == nullptr || h->g_ubar != ubar || h->g_mom != mom) {
+  // whole steps (three stages and the finish kernel) as graphs, captured
+  // once and replayed by every later call on the same state arrays
+  if (h->exec[0] == nullptr || h->g_ubar != ubar || h->g_mom != mom) {
     drop_graph(h);
-    hipGraph_t graph = nullptr;
-    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    int rc = HWENOU_OK;
-    do {
-      rc = launch_stage(h, 0, h->d_dt, h->d_alpha, h->d_done, ubar, mom, h->s1u, h->s1m, nullptr,
-                        st);
-      if (rc) break;
-      h->u_base = ubar;
-      rc = launch_stage(h, 1, h->d_dt, h->d_alpha, h->d_done, h->s1u, h->s1m, h->s2u, h->s2m,
-                        nullptr, st);
-      if (rc) break;
-      rc = launch_stage(h, 2, h->d_dt, h->d_alpha, h->d_done, h->s2u, h->s2m, ubar, mom,
-                        h->d_alpha_next, st);
-      if (rc) break;
-      if ((e = launch_finish(a, st)) != hipSuccess) {
-        rc = hip_fail(e, "finish launch");
-        break;
+    for (int g = 0; g < 2; ++g) {
+      const int nsteps = g == 0 ? 1 : kMultiSteps;
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      int rc = HWENOU_OK;
+      for (int q = 0; q < nsteps && rc == HWENOU_OK; ++q) {
+        rc = launch_stage(h, 0, h->d_dt, h->d_alpha, h->d_done, ubar, mom, h->s1u, h->s1m,
+                          nullptr, st);
+        if (rc) break;
+        h->u_base = ubar;
+        rc = launch_stage(h, 1, h->d_dt, h->d_alpha, h->d_done, h->s1u, h->s1m, h->s2u, h->s2m,
+                          nullptr, st);
+        if (rc) break;
+        rc = launch_stage(h, 2, h->d_dt, h->d_alpha, h->d_done, h->s2u, h->s2m, ubar, mom,
+                          h->d_alpha_next, st);
+        if (rc) break;
+        if ((e = launch_finish(a, st)) != hipSuccess) rc = hip_fail(e, "finish launch");
       }
-    } while (0);
-    e = hipStreamEndCapture(st, &graph);
-    if (rc) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rc;
+      e = hipStreamEndCapture(st, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        drop_graph(h);
+        return rc;
+      }
+      if (e != hipSuccess) {
+        drop_graph(h);
+        return hip_fail(e, "hipStreamEndCapture");
+      }
+      e = hipGraphInstantiate(&h->exec[g], graph, nullptr, nullptr, 0);
+      h->graph[g] = graph;
+      if (e != hipSuccess) {
+        h->exec[g] = nullptr;
+        drop_graph(h);
+        return hip_fail(e, "hipGraphInstantiate");
+      }
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&h->exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      h->exec = nullptr;
-      return hip_fail(e, "hipGraphInstantiate");
-    }
-    h->graph = graph;
     h->g_ubar = ubar;
     h->g_mom = mom;
   }
-  // Replays in chunks of growing length.  After each chunk the all-done flag
-  // is copied to a pinned slot; the host waits only for the flag of the chunk
+  // Replays in chunks of growing length (multi-step graphs, then single
+  // steps for the rest of a chunk).  After each chunk the all-done flag is
+  // copied to a pinned slot; the host waits only for the flag of the chunk
   // before, so the device never idles between chunks.  Steps replayed after
   // every instance is done are no-ops.
-  int launched = 0, chunk = 8, slot = 0, prev = -1;
+  int launched = 0, chunk = 2 * kMultiSteps, slot = 0, prev = -1;
   while (launched < max_steps && e == hipSuccess) {
     const int k = std::min(chunk, max_steps - launched);
-    for (int r = 0; r < k && e == hipSuccess; ++r) e = hipGraphLaunch(h->exec, st);
+    for (int r = 0; r + kMultiSteps <= k && e == hipSuccess; r += kMultiSteps)
+      e = hipGraphLaunch(h->exec[1], st);
+    for (int r = 0; r < k % kMultiSteps && e == hipSuccess; ++r) e = hipGraphLaunch(h->exec[0], st);
     if (e != hipSuccess) break;
     launched += k;
     e = hipMemcpyAsync(&h->h_flags[slot], h->d_all_done, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -674,7 +688,7 @@ int hwenou_advance(hwenou_handle* h, double* ubar, void* mom, double cfl, double
     }
     prev = slot;
     slot ^= 1;
-    chunk = std::min(2 * chunk, 256);
+    chunk = std::min(2 * chunk, 512);
   }
   h->u_base = nullptr;  // the steps' stage-0 launches overwrote the stored v^n
   if (e != hipSuccess) return hip_fail(e, "graph replay");

@@ -27,6 +27,15 @@ struct WorkItem {
 // the neighbouring cells whose interface values the strip needs.
 constexpr int kStripWidth = 62;
 
+// The last stage reduces the wave speeds of its output into kAlphaSlots
+// accumulators per instance and direction (the wave's block index picks
+// one), so that ~1000 waves ending together do not all serialise their
+// atomics on one address; the finish kernel takes the maximum of the slots.
+constexpr int kAlphaSlots = 8;
+__device__ __forceinline__ int alpha_slot(int inst, int block) {
+  return 2 * (inst * kAlphaSlots + (block & (kAlphaSlots - 1)));
+}
+
 template <class TM>
 struct StageArgs {
   SchemeParams P;
@@ -40,7 +49,7 @@ struct StageArgs {
   TM* m_base;           // v^_n (and w^_n): written by stage 0, read by stages 1, 2
   double* u_out;
   TM* m_out;
-  double* alpha_next;   // [n_inst][2] or nullptr: max wave speed of the output
+  double* alpha_next;   // [n_inst][kAlphaSlots][2] or nullptr: max wave speed of the output
   int* status;          // [n_inst]: set to 1 on a non-physical or non-finite output
   long long plane;      // cells per component plane
   const WorkItem* work;
@@ -92,7 +101,7 @@ struct AuxArgs {
   int* steps;            // [n_inst]
   int* done;             // [n_inst]
   int* status;           // [n_inst]: 1 once the instance left the physical states
-  double* alpha_next;    // [n_inst][2]
+  double* alpha_next;    // [n_inst][kAlphaSlots][2]
   const RunParams* run;  // CFL number, final time, step limit
   int* all_done;         // 1 when every instance is done
 };

@@ -627,8 +627,9 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
     if (ST == 2 && A.alpha_next != nullptr) {
       const double mx = wave_max(amax_x), my = wave_max(amax_y);
       if (lane == 0) {
-        atomic_max_nonneg(&A.alpha_next[2 * wk.inst], mx);
-        atomic_max_nonneg(&A.alpha_next[2 * wk.inst + 1], my);
+        double* acc = A.alpha_next + alpha_slot(wk.inst, blockIdx.x);
+        atomic_max_nonneg(acc, mx);
+        atomic_max_nonneg(acc + 1, my);
       }
     }
   }
