@@ -75,6 +75,7 @@ def load(path):
     L.oracle_num_threads.restype = C.c_int
     L.oracle_set_num_threads.argtypes = [C.c_int]
     L.oracle_eigvecs.argtypes = [C.POINTER(_Params), dp, C.c_int, C.c_int, dp, dp]
+    L.oracle_roe_state.argtypes = [C.POINTER(_Params), dp, dp, C.c_int, dp]
     # hand in the exactly derived operators
     r1 = derive.recon_1d()
     keep = [_flat(r1["M0"]), _flat(r1["M1"]), _flat(r1["M2"]), _flat(derive.beta_gram_1d(4)),
@@ -131,9 +132,13 @@ def _ptr(a):
 def _char_mode(c):
     """True / 1: direction-split characteristic sweeps; False / 0:
     component-wise; 2 or 'single': one x-characteristic reconstruction for
-    both directions."""
+    both directions; 3 or 'interface': split sweeps with the edge values at
+    each interface in the characteristic variables of the Roe average of the
+    two cells that share it (2D)."""
     if c == "single":
         return 2
+    if c == "interface":
+        return 3
     return int(c)
 
 
@@ -146,7 +151,9 @@ class Problem:
         (x-lo, x-hi[, y-lo, y-hi]).
     char_decomp (Euler): True / 1 direction-split characteristic sweeps (the
         default), False / 0 component-wise, 2 / 'single' one reconstruction in
-        x-characteristic variables for every output (2D).
+        x-characteristic variables for every output (2D), 3 / 'interface'
+        split sweeps with interface (Roe-average) bases for the edge values
+        (2D).
     """
 
     def __init__(self, dim, eq, n, domain, bc="periodic", gas_gamma=1.4, adv=(1.0, 1.0),
@@ -242,6 +249,18 @@ class Problem:
         if rc == ERR_NONPHYSICAL:
             raise NonPhysicalState("non-physical state")
         return R.reshape(n, n), Linv.reshape(n, n)
+
+    def roe_state(self, UL, UR):
+        """The conserved state at the Roe average of UL and UR (Euler) that
+        the per-interface projection takes its eigenvectors from."""
+        UL = np.ascontiguousarray(UL, dtype=np.float64)
+        UR = np.ascontiguousarray(UR, dtype=np.float64)
+        U = np.zeros(self.dim + 2)
+        rc = lib().oracle_roe_state(C.byref(self.params), _ptr(UL), _ptr(UR), self.dim,
+                                    _ptr(U))
+        if rc == ERR_NONPHYSICAL:
+            raise NonPhysicalState("non-physical state")
+        return U
 
     def check_physical(self, ubar):
         ubar = np.ascontiguousarray(ubar, dtype=np.float64)

@@ -24,12 +24,20 @@
  * f') yields the x-edge values, the interior values used for f and v^, and a
  * y-sweep (eigenvectors of g') the y-edge values, the interior values used
  * for g and w^.  L = R^{-1} is obtained here by Gauss-Jordan elimination.
+ * The remark leaves the state of the eigenvectors open; besides the cell's
+ * own average (the default), a per-interface variant takes the edge values
+ * at an interface in the characteristic variables of the Roe average of the
+ * two cells that share it, as the classical characteristic WENO schemes do,
+ * and keeps the cell's own average for the interior values and v^, w^.
  *
  * ORACLE_PLANT (test-only compile switch, never set in the library that the
  * tests and the benchmark load) plants one known mistake, so that the tests
  * can show that a pin fails on it: 1 = energy entry q^2 instead of q^2/2 in the
  * entropy eigenvector; 2 = the 2D tau averaged over 2 instead of the 4
- * differences; 3 = the 2D u_ave taken over all nine stencil cells.
+ * differences; 3 = the 2D u_ave taken over all nine stencil cells; 4 = the
+ * arithmetic mean of the two enthalpies in the Roe average; 5 = the edge
+ * values of each side of a cell taken in the basis of the interface on the
+ * other side (per-interface projection).
  */
 #ifndef ORACLE_PLANT
 #define ORACLE_PLANT 0
@@ -59,7 +67,10 @@ typedef struct {
   int char_decomp; /* Euler: 0 = component-wise; 1 = characteristic-wise, the
                       x-sweep in x-characteristic variables, the y-sweep in
                       y-characteristic variables; 2 = characteristic-wise with
-                      the single x-projection for every output (2D) */
+                      the single x-projection for every output (2D); 3 = as 1,
+                      but the edge values at each interface in the
+                      characteristic variables of the Roe average of the two
+                      cells that share it (2D) */
   double adv_x, adv_y;   /* advection velocity */
   double gas_gamma;      /* ratio of specific heats */
   double gamma_low;      /* linear weight of each linear polynomial */
@@ -284,6 +295,45 @@ static int euler_right_eigvecs(const oracle_params *P, const double *U, int dim,
       for (int k = 0; k < 4; ++k) R[r * 4 + k] = cols[k][r];
   }
   return 0;
+}
+
+/* Roe average of two conserved states (ideal gas): sqrt(rho)-weighted
+ * velocity and total enthalpy, returned as a conserved state with density
+ * sqrt(rho_L rho_R) and the energy that gives that enthalpy, so that
+ * euler_right_eigvecs sees u, v, H and c^2 = (gamma - 1)(H - q^2/2).
+ * Returns -1 on a non-physical input. */
+static int roe_state(const oracle_params *P, const double *UL, const double *UR, int dim,
+                     double *U) {
+  double gm = P->gas_gamma;
+  if (!(UL[0] > 0.0) || !(UR[0] > 0.0)) return -1;
+  double sl = sqrt(UL[0]), sr = sqrt(UR[0]);
+  double w = 1.0 / (sl + sr);
+  double q2 = 0.0, vel[2];
+  for (int d = 0; d < dim; ++d) {
+    vel[d] = (UL[1 + d] / sl + UR[1 + d] / sr) * w; /* (sl u_L + sr u_R)/(sl + sr) */
+    q2 += vel[d] * vel[d];
+  }
+  double hl = 0.0, hr = 0.0, ql = 0.0, qr = 0.0;
+  for (int d = 0; d < dim; ++d) {
+    ql += UL[1 + d] * UL[1 + d];
+    qr += UR[1 + d] * UR[1 + d];
+  }
+  double pl = (gm - 1.0) * (UL[dim + 1] - 0.5 * ql / UL[0]);
+  double pr = (gm - 1.0) * (UR[dim + 1] - 0.5 * qr / UR[0]);
+  if (!(pl > 0.0) || !(pr > 0.0)) return -1;
+  hl = (UL[dim + 1] + pl) / UL[0];
+  hr = (UR[dim + 1] + pr) / UR[0];
+  double H = ORACLE_PLANT == 4 ? 0.5 * (hl + hr) : (sl * hl + sr * hr) * w;
+  double rho = sl * sr;
+  U[0] = rho;
+  for (int d = 0; d < dim; ++d) U[1 + d] = rho * vel[d];
+  U[dim + 1] = (rho * H + (gm - 1.0) * 0.5 * rho * q2) / gm;
+  return 0;
+}
+
+int oracle_roe_state(const oracle_params *P, const double *UL, const double *UR, int dim,
+                     double *U) {
+  return roe_state(P, UL, UR, dim, U) ? ERR_NONPHYSICAL : 0;
 }
 
 /* The eigenvector basis the reconstruction projects with, for the tests:
@@ -536,6 +586,38 @@ static void recon_2d_scalar(const oracle_params *P, const double d[17], double p
   *what = w[0] * qw_in + qw_out;
 }
 
+/* Component-wise reconstruction of the 17 stencil vectors D[t][k]. */
+static void recon_components_2d(const oracle_params *P, double D[17][4], int nc,
+                                double pts[NPTS2][4], double *vh, double *wh) {
+  for (int ch = 0; ch < nc; ++ch) {
+    double d[17], p[NPTS2];
+    for (int t = 0; t < 17; ++t) d[t] = D[t][ch];
+    recon_2d_scalar(P, d, p, vh + ch, wh + ch);
+    for (int Pt = 0; Pt < NPTS2; ++Pt) pts[Pt][ch] = p[Pt];
+  }
+}
+
+/* Characteristic reconstruction of the 17 stencil vectors D[t][k] with the
+ * eigenvectors of the flux Jacobian in direction `sweep` at the state Uref:
+ * project with L = R^-1, reconstruct each field, map the point values and
+ * moments back with R.  Returns -1 on a non-physical Uref. */
+static int project_recon_2d(const oracle_params *P, double D[17][4], const double *Uref,
+                            int sweep, int nc, double pts[NPTS2][4], double *vh, double *wh) {
+  double R[16], L[16];
+  if (euler_right_eigvecs(P, Uref, 2, sweep, R) || invert(R, L, 4)) return -1;
+  double W[NPTS2][4], Wv[4], Ww[4];
+  for (int ch = 0; ch < nc; ++ch) {
+    double d[17], p[NPTS2];
+    for (int t = 0; t < 17; ++t) d[t] = dot(L + ch * 4, D[t], 4);
+    recon_2d_scalar(P, d, p, Wv + ch, Ww + ch);
+    for (int Pt = 0; Pt < NPTS2; ++Pt) W[Pt][ch] = p[Pt];
+  }
+  for (int Pt = 0; Pt < NPTS2; ++Pt) matvec(R, W[Pt], pts[Pt], 4, 4);
+  matvec(R, Wv, vh, 4, 4);
+  matvec(R, Ww, wh, 4, 4);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* 2D right-hand side                                                       */
 /* ------------------------------------------------------------------------ */
@@ -602,37 +684,45 @@ int oracle_rhs_2d(const oracle_params *P, int nx, int ny, double dx, double dy, 
       }
       int charwise = P->eq == EQ_EULER && P->char_decomp;
       int single = !charwise || P->char_decomp == 2; /* one reconstruction for both directions */
+      int iface = charwise && P->char_decomp == 3;   /* edge values in interface bases */
       for (int sweep = 0; sweep < (single ? 1 : 2); ++sweep) {
-        double R[16], L[16];
+        double pts[NPTS2][4], vh[4], wh[4];
         if (charwise) {
-          double U5[4];
-          for (int k = 0; k < 4; ++k) U5[k] = D[4][k];
-          if (euler_right_eigvecs(P, U5, 2, sweep, R) || invert(R, L, 4)) {
+          if (project_recon_2d(P, D, D[4], sweep, nc, pts, vh, wh)) {
             bad |= 1;
             break;
           }
+        } else {
+          recon_components_2d(P, D, nc, pts, vh, wh);
         }
-        double pts[NPTS2][4], vh[4], wh[4];
-        for (int ch = 0; ch < nc; ++ch) {
-          double d[17];
-          for (int t = 0; t < 17; ++t) d[t] = charwise ? dot(L + ch * 4, D[t], 4) : D[t][ch];
-          double p[NPTS2];
-          recon_2d_scalar(P, d, p, vh + ch, wh + ch);
-          for (int Pt = 0; Pt < NPTS2; ++Pt) pts[Pt][ch] = p[Pt];
-        }
-        if (charwise) { /* back to conserved variables */
-          for (int Pt = 0; Pt < NPTS2; ++Pt) {
-            double tmp[4];
-            matvec(R, pts[Pt], tmp, 4, 4);
-            for (int k = 0; k < 4; ++k) pts[Pt][k] = tmp[k];
+        if (iface) {
+          /* edge values of the low and high side of this sweep's direction
+           * in the bases of the Roe averages with the neighbours there
+           * (cells 4 and 6 in x, 2 and 8 in y) */
+          int lo = sweep == 0 ? 3 : 1, hi = sweep == 0 ? 5 : 7;
+          if (ORACLE_PLANT == 5) {
+            const int t = lo;
+            lo = hi;
+            hi = t;
           }
-          double tv[4], tw[4];
-          matvec(R, vh, tv, 4, 4);
-          matvec(R, wh, tw, 4, 4);
-          for (int k = 0; k < 4; ++k) {
-            vh[k] = tv[k];
-            wh[k] = tw[k];
+          const int e_lo = sweep == 0 ? 0 : 6, e_hi = sweep == 0 ? 3 : 9;
+          double Ur[4], q[NPTS2][4], qv[4], qw[4];
+          if ((ORACLE_PLANT == 5 ? roe_state(P, D[4], D[lo], 2, Ur)
+                                 : roe_state(P, D[lo], D[4], 2, Ur)) ||
+              project_recon_2d(P, D, Ur, sweep, nc, q, qv, qw)) {
+            bad |= 1;
+            break;
           }
+          for (int e = 0; e < 3; ++e)
+            for (int k = 0; k < nc; ++k) pts[e_lo + e][k] = q[e_lo + e][k];
+          if ((ORACLE_PLANT == 5 ? roe_state(P, D[hi], D[4], 2, Ur)
+                                 : roe_state(P, D[4], D[hi], 2, Ur)) ||
+              project_recon_2d(P, D, Ur, sweep, nc, q, qv, qw)) {
+            bad |= 1;
+            break;
+          }
+          for (int e = 0; e < 3; ++e)
+            for (int k = 0; k < nc; ++k) pts[e_hi + e][k] = q[e_hi + e][k];
         }
         int do_x = single || sweep == 0;
         int do_y = single || sweep == 1;

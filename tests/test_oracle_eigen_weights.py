@@ -239,3 +239,101 @@ def test_tau_pin_fails_on_a_planted_divisor(planted):
     with driver.using(planted[2]):
         gap, _, _ = _tau_pin_gap()
     assert gap > 1e-4, gap
+
+
+# ---------------------------------------------------------------------------
+# per-interface projection: the Roe average and its bases
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def planted_iface(tmp_path_factory):
+    d = tmp_path_factory.mktemp("planted_iface")
+    return {k: driver.load(obuild.build(out=str(d / f"liboracle_plant{k}.so"), plant=k))
+            for k in (4, 5)}
+
+
+def _roe_residual(seed):
+    """max over random state pairs and both 2D directions of
+    |A(U_roe)(U_R - U_L) - (F(U_R) - F(U_L))| / |F(U_R) - F(U_L)|, and of
+    |Roe(U, U) - U| / |U|."""
+    P = Problem(2, "euler", (8, 8), (0, 1, 0, 1))
+    states = _states(seed, 2, 16)
+    worst, same = 0.0, 0.0
+    for UL, UR in zip(states[::2], states[1::2]):
+        Ur = P.roe_state(UL, UR)
+        for direction in (0, 1):
+            A = _jacobian(Ur, 2, direction)
+            dF = _flux(UR, 2, direction) - _flux(UL, 2, direction)
+            worst = max(worst, np.abs(A @ (UR - UL) - dF).max() / np.abs(dF).max())
+        same = max(same, np.abs(P.roe_state(UL, UL) - UL).max() / np.abs(UL).max())
+    return worst, same
+
+
+def test_roe_average_linearises_the_flux():
+    """The Roe average (the textbook property that defines it): the flux
+    Jacobian at the averaged state maps the jump of the conserved variables
+    onto the jump of the flux exactly, in both directions; and it is
+    consistent, Roe(U, U) = U."""
+    worst, same = _roe_residual(1300)
+    assert worst <= 1e-13, worst
+    assert same <= 1e-15, same
+
+
+def test_roe_pin_fails_on_a_planted_enthalpy_mean(planted_iface):
+    with driver.using(planted_iface[4]):
+        worst, _ = _roe_residual(1300)
+    assert worst > 1e-4, worst
+
+
+def _blocks_case(seed, nx=16, ny=4, width=4):
+    """y-constant data whose averages are constant on blocks of `width`
+    columns (states within 5% of rho = p = 1 at rest, so that the weights
+    stay away from the one-sided limits where every basis gives the same
+    constant) and whose x-moments are random, up to 10% of the averages."""
+    rng = np.random.default_rng(seed)
+    u = np.zeros((4, ny, nx))
+    for b in range(0, nx, width):
+        rho, vx, vy, p = 1.0 + 0.05 * rng.uniform(-1, 1, 4) - np.array([0.0, 1.0, 1.0, 0.0])
+        u[:, :, b:b + width] = np.array([rho, rho * vx, rho * vy,
+                                         p / 0.4 + 0.5 * rho * (vx * vx + vy * vy)])[:, None, None]
+    m = np.zeros((2, 4, ny, nx))
+    m[0] = rng.uniform(-0.1, 0.1, (4, 1, nx)) * np.abs(u[:, :1, :])
+    return u, m
+
+
+def _iface_block_gap(seed=1400, width=4):
+    """Largest relative F1 difference between the per-interface and the
+    split schemes over the cells whose two x-interfaces lie inside a block
+    of equal averages (there every interface basis is the cells' own one),
+    and the smallest one over the cells next to a block edge."""
+    u, m = _blocks_case(seed, width=width)
+    nx = u.shape[2]
+    out = {}
+    for mode in (1, 3):
+        P = Problem(2, "euler", (nx, u.shape[1]), (0, 10, 0, 2.5), char_decomp=mode)
+        out[mode] = P.rhs(u, m, P.max_wavespeed(u))
+    d = np.abs(out[3][0] - out[1][0]).max(axis=(0, 1)) / np.abs(out[1][0]).max()
+    inner = [i for i in range(nx) if 0 < i % width < width - 1]
+    edge = [i for i in range(nx) if i % width in (0, width - 1)]
+    same_vhat = np.abs(out[3][2] - out[1][2]).max()
+    return float(d[inner].max()), float(d[edge].min()), float(same_vhat)
+
+
+def test_interface_bases_are_shared_by_both_sides():
+    """Both sides of an interface are reconstructed in the basis of that
+    interface (the Roe average of the two cells), and the interior values and
+    v^, w^ in the cell's own one: wherever two neighbours have equal
+    averages, their interface's basis is their own, so the per-interface
+    scheme equals the split scheme at every cell whose two interfaces lie
+    inside a block of equal averages (to rounding), differs next to the
+    block edges, and has the same v^, w^ everywhere."""
+    inner, edge, same_vhat = _iface_block_gap()
+    assert inner <= 1e-12, inner  # measured 5e-15
+    assert edge > 1e-6, edge  # measured 6e-5
+    assert same_vhat == 0.0
+
+
+def test_interface_pin_fails_on_planted_swapped_bases(planted_iface):
+    with driver.using(planted_iface[5]):
+        inner, _, _ = _iface_block_gap()
+    assert inner > 1e-5, inner  # measured 1e-3

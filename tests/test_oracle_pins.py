@@ -538,10 +538,15 @@ def test_reflective_walls_equal_mirror_extended_periodic_2d():
     assert np.abs(T1 - F1).max() > 1e-3 * np.abs(F1).max()
 
 
-def test_transpose_symmetry_2d_euler():
+@pytest.mark.parametrize("mode", [1, 3])
+def test_transpose_symmetry_2d_euler(mode):
+    """Swapping x and y (with the momenta, the moments and the wave speeds)
+    maps the right-hand side onto itself: the y-part of the scheme is the
+    x-part turned by 90 degrees, for the split sweeps (1) and for the
+    per-interface bases (3)."""
     n = 10
     u, m = W.euler_2d_vortex_quadrant(n, seed=32, q=2)
-    P = Problem(2, "euler", (n, n), (0, 10, 0, 10))
+    P = Problem(2, "euler", (n, n), (0, 10, 0, 10), char_decomp=mode)
     perm = [0, 2, 1, 3]  # swap momenta
     ut = u[perm].transpose(0, 2, 1).copy()
     mt = m[::-1][:, perm].transpose(0, 1, 3, 2).copy()
@@ -555,15 +560,36 @@ def test_transpose_symmetry_2d_euler():
                                atol=1e-11)
 
 
+@pytest.mark.parametrize("mode", [1, 3])
+def test_x_mirror_symmetry_2d_euler(mode):
+    """Mirroring the periodic grid in x (x-momentum and x-moments negated,
+    the x-moment of the x-momentum twice) mirrors the right-hand side: the
+    left and right edges of a cell are treated alike, and for the
+    per-interface bases each edge takes the basis of its own interface (the
+    Roe average is symmetric in its two states)."""
+    n = 10
+    u, m = W.euler_2d_vortex_quadrant(n, seed=33, q=2)
+    P = Problem(2, "euler", (n, n), (0, 10, 0, 10), char_decomp=mode)
+    um, mm = _mirror_x(u, m, 2, 3)
+    al = P.max_wavespeed(u)
+    F1, Fm, mh = P.rhs(u, m, al)
+    G1, Gm, gh = P.rhs(np.ascontiguousarray(um), np.ascontiguousarray(mm), al)
+    a1, am = _mirror_x(F1, Fm, 2, 3)
+    _, ah = _mirror_x(F1, mh, 2, 3)
+    np.testing.assert_allclose(G1, a1, rtol=1e-11, atol=1e-11 * np.abs(F1).max())
+    np.testing.assert_allclose(Gm, am, rtol=1e-11, atol=1e-11 * np.abs(Fm).max())
+    np.testing.assert_allclose(gh, ah, rtol=1e-11, atol=1e-11 * np.abs(mh).max())
+
+
 def test_projection_modes_agree_with_linear_weights():
     """With linear weights the reconstruction is linear and commutes with any
     invertible projection, so component-wise, direction-split
-    characteristic and single-projection characteristic reconstruction give
-    the same right-hand side (to rounding)."""
+    characteristic, single-projection characteristic and per-interface
+    reconstruction give the same right-hand side (to rounding)."""
     n = 12
     u, m = W.euler_2d_vortex_quadrant(n, seed=63, q=2)
     outs = []
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3):
         P = Problem(2, "euler", (n, n), (0, 10, 0, 10), weights="linear", char_decomp=mode)
         outs.append(P.rhs(u, m, P.max_wavespeed(u)))
     for a in outs[1:]:
