@@ -12,7 +12,8 @@ form (`value`, the paper's precision) and, in a block of its own, of the
 FP32+FP64 mixed form with its speed-up and its L1 difference from FP64 after
 the timed run next to the FP64 difference between the 1024^2 and 2048^2
 solutions at the same time; the same rates for component-wise
-reconstruction and for one x-characteristic reconstruction per cell; the
+reconstruction, for one x-characteristic reconstruction per cell and for
+per-interface (Roe-average) bases of the edge values; the
 stage kernel's roofline position, from its average launch duration measured
 with HIP events on the stream its launches run on; and the CPU oracle on a
 bounded sample.
@@ -462,6 +463,13 @@ def main():
             sp[prec] = {"value": rc["rate"], "ms_per_step": rc["ms_per_step"],
                         "status": rc["status"]}
         line["single_projection"] = sp
+        ip = {}
+        for prec in precs:
+            print(f"[bench] per-interface bases {prec}", file=sys.stderr, flush=True)
+            rc = run_case(H, torch, case, prec, steps, args.warmup, False, char_decomp=3)
+            ip[prec] = {"value": rc["rate"], "ms_per_step": rc["ms_per_step"],
+                        "status": rc["status"]}
+        line["interface_projection"] = ip
         if "fp64" in results and n % 2 == 0 and "mixed_vs_fp64" in line:
             print("[bench] FP64 mesh difference", file=sys.stderr, flush=True)
             tf = results["fp64"]["t"][0]

@@ -58,12 +58,22 @@ enum { HWENOU_FP64 = 0, HWENOU_MIXED = 1 };
 /* nonlinear weights: scale-invariant (Eq. (2.8)/(2.14)), the scale-dependent
  * original (u_ave = 1, Remark 2.1 of Section 2.1), or linear (w = gamma). */
 enum { HWENOU_W_SCALE_INVARIANT = 0, HWENOU_W_ZQ = 1, HWENOU_W_LINEAR = 2 };
-/* Euler reconstruction variables (Remark 2.1): conserved variables
- * (component-wise); local characteristic variables in direction-split sweeps
- * (x-edges, f and v^ from the x-projection, y-edges, g and w^ from the
- * y-projection; the default); or one reconstruction in x-characteristic
- * variables for every output (2D; the same as SPLIT in 1D). */
-enum { HWENOU_CHAR_COMPONENT = 0, HWENOU_CHAR_SPLIT = 1, HWENOU_CHAR_SINGLE = 2 };
+/* Euler reconstruction variables (the local characteristic decomposition of
+ * Remark 2.2, which leaves the state of the eigenvectors open): conserved
+ * variables (component-wise); local characteristic variables at the cell's
+ * own average in direction-split sweeps (x-edges, f and v^ from the
+ * x-projection, y-edges, g and w^ from the y-projection; the default); one
+ * reconstruction in x-characteristic variables for every output (2D; the
+ * same as SPLIT in 1D); or the split sweeps with the edge values at each
+ * interface in the characteristic variables of the Roe average of the two
+ * cells that share it, the interior values and v^, w^ at the cell's own
+ * average (2D Euler only; three reconstructions per cell and direction). */
+enum {
+  HWENOU_CHAR_COMPONENT = 0,
+  HWENOU_CHAR_SPLIT = 1,
+  HWENOU_CHAR_SINGLE = 2,
+  HWENOU_CHAR_INTERFACE = 3
+};
 /* boundary conditions per side: periodic; transmissive (outflow: ghost cells
  * copy the boundary cell); reflective (Euler only: a solid wall, ghost cells
  * are mirror images with the wall-normal momentum negated and the moments

@@ -34,8 +34,9 @@ EQ = {"advection": 0, "burgers": 1, "euler": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 WEIGHTS = {"scale_invariant": 0, "zq": 1, "linear": 2}
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
-# Euler reconstruction variables: True / 1 = "split" (default), False / 0, 2 = "single"
-CHAR = {"component": 0, "split": 1, "single": 2}
+# Euler reconstruction variables: True / 1 = "split" (default), False / 0, 2 = "single",
+# 3 = "interface"
+CHAR = {"component": 0, "split": 1, "single": 2, "interface": 3}
 
 EXPORTS = ["hwenou_create", "hwenou_destroy", "hwenou_strerror", "hwenou_max_wavespeed",
            "hwenou_stage", "hwenou_advance", "hwenou_status", "hwenou_inst_status",

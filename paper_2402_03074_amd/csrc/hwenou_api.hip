@@ -310,7 +310,9 @@ int check_desc(const hwenou_desc* d) {
   if (d->eq < HWENOU_EQ_ADVECTION || d->eq > HWENOU_EQ_EULER) return HWENOU_EINVAL;
   if (d->precision != HWENOU_FP64 && d->precision != HWENOU_MIXED) return HWENOU_EINVAL;
   if (d->weights < HWENOU_W_SCALE_INVARIANT || d->weights > HWENOU_W_LINEAR) return HWENOU_EINVAL;
-  if (d->char_decomp < HWENOU_CHAR_COMPONENT || d->char_decomp > HWENOU_CHAR_SINGLE)
+  if (d->char_decomp < HWENOU_CHAR_COMPONENT || d->char_decomp > HWENOU_CHAR_INTERFACE)
+    return HWENOU_EINVAL;
+  if (d->char_decomp == HWENOU_CHAR_INTERFACE && d->eq == HWENOU_EQ_EULER && d->dim != 2)
     return HWENOU_EINVAL;
   if (!(d->gamma_low > 0.0) || d->gamma_low * (d->dim == 1 ? 2 : 4) >= 1.0) return HWENOU_EINVAL;
   if (!(d->eps >= 0.0)) return HWENOU_EINVAL;

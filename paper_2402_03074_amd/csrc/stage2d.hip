@@ -58,6 +58,33 @@ __device__ __forceinline__ Prim make_prim(double gm1, const double (&U)[4]) {
   return p;
 }
 
+// The same quantities at the Roe average of two cell averages (the
+// per-interface bases): sqrt(rho)-weighted velocity and total enthalpy,
+// c^2 = (gamma - 1)(H - q^2 / 2).  The arguments come in a fixed order (the
+// lower or left cell first), so the two cells that share an interface form
+// bitwise the same basis.
+template <class TR>
+__device__ __forceinline__ Prim make_prim_roe(double gm1, const double (&UL)[4],
+                                              const double (&UR)[4]) {
+  Prim p;
+  const double il = rsq_w<TR>(UL[0]), ir = rsq_w<TR>(UR[0]);  // 1/sqrt(rho)
+  const double sl = UL[0] * il, sr = UR[0] * ir;                 // sqrt(rho)
+  const double w = rcp_w<TR>(sl + sr);
+  p.u = (UL[1] * il + UR[1] * ir) * w;
+  p.v = (UL[2] * il + UR[2] * ir) * w;
+  p.q2 = p.u * p.u + p.v * p.v;
+  // sqrt(rho) H = (E + p) / sqrt(rho), with p = (gamma - 1)(E - |m|^2 / (2 rho))
+  const double hl = (UL[3] + gm1 * (UL[3] - 0.5 * (UL[1] * UL[1] + UL[2] * UL[2]) * il * il)) * il;
+  const double hr = (UR[3] + gm1 * (UR[3] - 0.5 * (UR[1] * UR[1] + UR[2] * UR[2]) * ir * ir)) * ir;
+  p.H = (hl + hr) * w;
+  const double c2 = gm1 * (p.H - 0.5 * p.q2);
+  p.ci = rsq_w<TR>(c2);
+  p.c = c2 * p.ci;
+  p.b1 = gm1 * (p.ci * p.ci);
+  p.b2 = 0.5 * p.b1 * p.q2;
+  return p;
+}
+
 // Row k of the left eigenvectors and column k of the right eigenvectors of
 // the Euler flux Jacobian in direction DIR (ideal gas):
 // x: R = [(1,u-c,v,H-uc), (1,u,v,q^2/2), (0,0,1,v), (1,u+c,v,H+uc)]
@@ -274,7 +301,11 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
 }
 
 // CHAR (Euler): 0 component-wise; 1 direction-split characteristic sweeps;
-// 2 one reconstruction in x-characteristic variables for every output.
+// 2 one reconstruction in x-characteristic variables for every output;
+// 3 as 1, with the edge values at each interface reconstructed in the basis
+// of the Roe average of the two cells that share it (three reconstructions
+// per cell and direction: low interface, high interface, own average for the
+// interior values and the moment).
 // SI: scale-invariant weights compiled in (else the mode comes from P).
 // ST: the Runge-Kutta stage (0, 1, 2), so that its coefficients and the
 // stage-0-only stores are compiled in.
@@ -284,9 +315,13 @@ template <int EQ, int CHAR, bool SI, int ST, class TR, class TM>
 __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 4 : 1;
   constexpr bool PROJ = EQ == EQ_EULER && CHAR != 0;   // characteristic variables
-  constexpr bool SPLIT = EQ == EQ_EULER && CHAR == 1;  // a second, x-direction sweep
+  constexpr bool SPLIT = EQ == EQ_EULER && (CHAR == 1 || CHAR == 3);  // an x-direction sweep
+  constexpr bool IFACE = EQ == EQ_EULER && CHAR == 3;  // interface bases for edge values
   __shared__ RowBuf<NC, TM> B;
   __shared__ TR c1buf[16][64];  // entropy-field polynomial shared by the two sweeps
+  // per-interface bases: the edge values of the low and the high edge of the
+  // current direction, parked while the cell's own basis is reconstructed
+  __shared__ TR ebuf[IFACE ? 2 * 3 * NC : 1][64];
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   if (w >= A.n_waves) return;
@@ -435,7 +470,51 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
       // ---- reconstruction of row j, y-direction ----
       TR Cc[NC][15];
       Prim pr;
-      if constexpr (PROJ) {
+      if constexpr (IFACE) {
+        auto roe_rows = [&](int sl, int sr) {  // Roe basis of rows sl (below) and sr (above)
+          double UL[4], UR[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            UL[k] = B.u[sl][k][lane + 1];
+            UR[k] = B.u[sr][k][lane + 1];
+          }
+          return make_prim_roe<TR>(gm1, UL, UR);
+        };
+        // top edge, eta = +1/2, in the basis of y_{j+1/2}
+        char_sweep<1, SI, false, TR, TM>(P, roe_rows(sc, st), B, sb, sc, st, lane, Cc, c1buf,
+                                         false);
+#pragma unroll
+        for (int G = 0; G < 3; ++G)
+#pragma unroll
+          for (int k = 0; k < NC; ++k) {
+            TR d[5], e0, e1, g0, g1, g2;
+            restrict_xi<TR>(Cc[k], (TR)g3x(G), d);
+            eval5<TR>(d, e0, e1, g0, g1, g2);
+            ebuf[(3 + G) * NC + k][lane] = e1;
+          }
+        __builtin_amdgcn_sched_barrier(0);
+        if (j >= r0) {
+          // bottom edge, eta = -1/2, in the basis of y_{j-1/2}
+          char_sweep<1, SI, false, TR, TM>(P, roe_rows(sb, sc), B, sb, sc, st, lane, Cc, c1buf,
+                                           false);
+#pragma unroll
+          for (int G = 0; G < 3; ++G)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+              TR d[5], e0, e1, g0, g1, g2;
+              restrict_xi<TR>(Cc[k], (TR)g3x(G), d);
+              eval5<TR>(d, e0, e1, g0, g1, g2);
+              ebuf[G * NC + k][lane] = e0;
+            }
+          __builtin_amdgcn_sched_barrier(0);
+          // interior values and w^ in the cell's own basis
+          double U5[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
+          pr = make_prim<TR>(gm1, U5);
+          char_sweep<1, SI, true, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, false);
+        }
+      } else if constexpr (PROJ) {
         double U5[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
@@ -473,6 +552,10 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
           TR d[5];
           restrict_xi<TR>(Cc[k], xg, d);
           eval5<TR>(d, ym[k], yp[k], in[0][k], in[1][k], in[2][k]);
+          if constexpr (IFACE) {
+            ym[k] = ebuf[G * NC + k][lane];
+            yp[k] = ebuf[(3 + G) * NC + k][lane];
+          }
         }
         if (row_out) {
 #pragma unroll
@@ -558,6 +641,47 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 
       if (row_out) {
         // ---- x-direction reconstruction of row j ----
+        if constexpr (IFACE) {
+          auto roe_cols = [&](int cl) {  // Roe basis of columns cl (left) and cl + 1
+            double UL[4], UR[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              UL[k] = B.u[sc][k][lane + cl];
+              UR[k] = B.u[sc][k][lane + cl + 1];
+            }
+            return make_prim_roe<TR>(gm1, UL, UR);
+          };
+          // left edge, xi = -1/2, in the basis of x_{i-1/2}
+          char_sweep<0, SI, false, TR, TM>(P, roe_cols(0), B, sb, sc, st, lane, Cc, c1buf,
+                                           false);
+#pragma unroll
+          for (int H = 0; H < 3; ++H)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+              TR d[5], e0, e1, g0, g1, g2;
+              restrict_eta<TR>(Cc[k], (TR)g3x(H), d);
+              eval5<TR>(d, e0, e1, g0, g1, g2);
+              ebuf[H * NC + k][lane] = e0;
+            }
+          __builtin_amdgcn_sched_barrier(0);
+          // right edge, xi = +1/2, in the basis of x_{i+1/2}
+          char_sweep<0, SI, false, TR, TM>(P, roe_cols(1), B, sb, sc, st, lane, Cc, c1buf,
+                                           false);
+#pragma unroll
+          for (int H = 0; H < 3; ++H)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+              TR d[5], e0, e1, g0, g1, g2;
+              restrict_eta<TR>(Cc[k], (TR)g3x(H), d);
+              eval5<TR>(d, e0, e1, g0, g1, g2);
+              ebuf[(3 + H) * NC + k][lane] = e1;
+            }
+          __builtin_amdgcn_sched_barrier(0);
+          double U5[4];  // the own primitives again (cheaper than keeping them live)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
+          pr = make_prim<TR>(gm1, U5);
+        }
         if constexpr (SPLIT)
           char_sweep<0, SI, false, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, true);
         double F1x[NC];
@@ -576,6 +700,10 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
             TR d[5];
             restrict_eta<TR>(Cc[k], yh, d);
             eval5<TR>(d, xm[k], xp[k], in[0][k], in[1][k], in[2][k]);
+            if constexpr (IFACE) {
+              xm[k] = ebuf[H * NC + k][lane];
+              xp[k] = ebuf[(3 + H) * NC + k][lane];
+            }
           }
           if constexpr (SPLIT) {
 #pragma unroll
@@ -661,6 +789,7 @@ static hipError_t launch_t(int eq, int char_mode, const void* args, int blocks, 
     case EQ_ADVECTION: return launch<EQ_ADVECTION, 0, SI, TR, TR>(args, blocks, threads, s);
     case EQ_BURGERS: return launch<EQ_BURGERS, 0, SI, TR, TR>(args, blocks, threads, s);
     default:
+      if (char_mode == 3) return launch<EQ_EULER, 3, SI, TR, TR>(args, blocks, threads, s);
       if (char_mode == 2) return launch<EQ_EULER, 2, SI, TR, TR>(args, blocks, threads, s);
       return char_mode ? launch<EQ_EULER, 1, SI, TR, TR>(args, blocks, threads, s)
                        : launch<EQ_EULER, 0, SI, TR, TR>(args, blocks, threads, s);
@@ -699,6 +828,7 @@ static int occupancy_t(int eq, int char_mode, int threads) {
     case EQ_ADVECTION: return occupancy<EQ_ADVECTION, 0, SI, TR>(threads);
     case EQ_BURGERS: return occupancy<EQ_BURGERS, 0, SI, TR>(threads);
     default:
+      if (char_mode == 3) return occupancy<EQ_EULER, 3, SI, TR>(threads);
       if (char_mode == 2) return occupancy<EQ_EULER, 2, SI, TR>(threads);
       return char_mode ? occupancy<EQ_EULER, 1, SI, TR>(threads)
                        : occupancy<EQ_EULER, 0, SI, TR>(threads);

@@ -165,3 +165,10 @@ def test_no_alloc_step_rejects_bad_arguments_without_a_device():
     off = H.make_inst(10, 10, (0, 1, 0, 1), offset=5)  # one instance, at offset 0 only
     assert L.hwenou_step_noalloc(C.byref(d), C.byref(off), None, one, one, one, one,
                                  None) == H.HWENOU_EINVAL
+
+
+def test_create_rejects_interface_bases_in_1d():
+    """The per-interface projection is a 2D Euler mode."""
+    d = H.make_desc(1, "euler", char_decomp="interface")
+    rc, h = _create(d, [H.make_inst(10)])
+    assert rc == H.HWENOU_EINVAL and not h.value

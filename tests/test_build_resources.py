@@ -33,10 +33,10 @@ def _usage(src):
 
 @pytest.mark.skipif(not os.path.exists(B.HIPCC), reason="hipcc not installed")
 # scalar laws (2) and Euler component-wise / characteristic, in 2 precisions;
-# 2D adds the single-projection Euler kernels and compiles each kernel twice,
+# 2D adds the single-projection and per-interface Euler kernels and compiles each kernel twice,
 # with the scale-invariant weights built in and with the mode read at run time,
 # for each of the three Runge-Kutta stages
-@pytest.mark.parametrize("src,count", [("stage2d.hip", 60), ("stage1d.hip", 24)])
+@pytest.mark.parametrize("src,count", [("stage2d.hip", 72), ("stage1d.hip", 24)])
 def test_stage_kernels_use_no_scratch(src, count):
     usage = _usage(src)
     kernels = {k: v for k, v in usage.items() if "stage" in k}

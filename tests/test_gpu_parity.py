@@ -52,6 +52,13 @@ def _cases():
     u, m = W.euler_2d_vortex_quadrant(130, 70, seed=3004, q=2)
     out.append(("euler2d_quad_130x70_single",
                 Problem(2, "euler", (130, 70), (0, 10, 0, 10), char_decomp=2), u, m))
+    u, m = W.euler_2d_vortex_quadrant(130, 70, seed=3005, q=2)
+    out.append(("euler2d_quad_130x70_interface",
+                Problem(2, "euler", (130, 70), (0, 10, 0, 10), char_decomp=3), u, m))
+    u, m = W.euler_2d_vortex_quadrant(67, 40, seed=3006, q=2)
+    out.append(("euler2d_quad_67x40_walls_interface",
+                Problem(2, "euler", (67, 40), (0, 10, 0, 10), char_decomp=3,
+                        bc=("reflective", "transmissive", "reflective", "transmissive")), u, m))
     return out
 
 
