@@ -359,3 +359,82 @@ def test_degenerate_sizes_one_step(case, precision):
             eu, em = state_err(P, got[s], ref[s], floor=1e-3)
             assert eu <= TOL_STAGE and em <= TOL_STAGE, (name, s, eu, em)
     S.close()
+
+
+def test_full_size_2d_euler_full_step_sampled_cells():
+    """The 2048^2 benchmark workload: one whole Runge-Kutta step (the three
+    stage kernels) on the GPU, in the launch shape bench.py times; 24 sampled
+    cells recomputed by the oracle on 15x15 periodic patches (after three
+    stages a cell depends on its 13x13 neighbourhood, and the wrap of the
+    patch reaches at most 6 cells in from its edge)."""
+    import torch
+    import paper_2402_03074_amd as H
+    n, r = 2048, 7
+    print("[gpu] full-size 2D full-step sampled parity", flush=True)
+    u0, m0 = W.euler_2d_vortex_quadrant(n, seed=3000, q=3)
+    P = Problem(2, "euler", (n, n), (0.0, 10.0, 0.0, 10.0))
+    alpha = P.max_wavespeed(u0)
+    dt = P.dt_from(alpha, 0.6)
+    S = H.Solver(2, "euler", [H.make_inst(n, n, (0.0, 10.0, 0.0, 10.0))])
+    ug = torch.tensor(u0.reshape(4, -1), device="cuda")
+    mg = torch.tensor(m0.reshape(2, 4, -1), device="cuda")
+    al = torch.tensor([[alpha[0], alpha[1]]], dtype=torch.float64, device="cuda")
+    dtg = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    u1, m1 = S.empty_state()
+    u2, m2 = S.empty_state()
+    u3, m3 = S.empty_state()
+    S.stage(0, dtg, al, ug, mg, u1, m1)
+    S.stage(1, dtg, al, u1, m1, u2, m2)
+    S.stage(2, dtg, al, u2, m2, u3, m3)
+    torch.cuda.synchronize()
+    got_u = u3.cpu().numpy().reshape(4, n, n)
+    got_m = m3.cpu().numpy().reshape(2, 4, n, n)
+    S.close()
+    rng = np.random.default_rng(78)
+    pts = [(int(a), int(b)) for a, b in rng.integers(0, n, size=(22, 2))] + [(0, 0), (2047, 1)]
+    h = 10.0 / n
+    Pp = Problem(2, "euler", (2 * r + 1, 2 * r + 1), (0.0, (2 * r + 1) * h, 0.0, (2 * r + 1) * h))
+    for (j, i) in pts:
+        rows = [(j + d) % n for d in range(-r, r + 1)]
+        cols = [(i + d) % n for d in range(-r, r + 1)]
+        pu = np.ascontiguousarray(u0[:, rows][:, :, cols])
+        pm = np.ascontiguousarray(m0[:, :, rows][:, :, :, cols])
+        u_, m_, base = Pp.stage(0, dt, alpha, pu, pm)
+        u_, m_, _ = Pp.stage(1, dt, alpha, u_, m_, base)
+        u_, m_, _ = Pp.stage(2, dt, alpha, u_, m_, base)
+        for k in range(4):
+            scale = np.abs(u0[k]).max()
+            assert abs(got_u[k, j, i] - u_[k, r, r]) <= TOL_STAGE * scale, (j, i, k)
+            for d in range(2):
+                mscale = np.abs(m0[d, k]).max()
+                assert abs(got_m[d, k, j, i] - m_[d, k, r, r]) <= TOL_STAGE * mscale, (j, i, k, d)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_zero_average_stencils(precision):
+    """Stencils whose five-cell cross has zero averages (u_ave = 0: the
+    nonlinear weights reduce to the linear ones, by the remark after
+    Eq. (2.11)) on the GPU: averages non-zero only on a lattice of every third
+    cell in x and y, so every cell at (1, 1) mod 3 has a zero cross and
+    non-zero corners; random moments.  One step against the oracle."""
+    n = 33
+    rng = np.random.default_rng(91)
+    u = np.zeros((1, n, n))
+    u[0, ::3, ::3] = rng.uniform(0.5, 1.5, (11, 11)) * rng.choice([-1.0, 1.0], (11, 11))
+    m = rng.uniform(-0.2, 0.2, (2, 1, n, n))
+    P = Problem(2, "advection", (n, n), (0, 1, 0, 1), adv=(1.0, -0.5))
+    alpha = P.max_wavespeed(u)
+    dt = P.dt_from(alpha, 0.4)
+    print(f"[gpu] zero-average stencils {precision}", flush=True)
+    ref = oracle_three_stages(P, u, m, dt, alpha)
+    S = solver_for(P, precision=precision)
+    if precision == "fp64":
+        got = gpu_three_stages(S, P, u, m, dt, alpha, inputs=ref[:2])
+        for s in range(3):
+            eu, em = state_err(P, got[s], ref[s])
+            assert eu <= TOL_STAGE and em <= TOL_STAGE, (s, eu, em)
+    else:
+        got = gpu_three_stages(S, P, u, m.astype(np.float32).astype(np.float64), dt, alpha,
+                               inputs=ref[:2])
+        assert_mixed_stage_close("zero_average", P, u, dt, alpha, got, ref)
+    S.close()
