@@ -10,11 +10,11 @@
  *     u_ij, v_ij, w_ij);
  *   - spatial operator: Steps 1-3 of Sections 2.1 / 2.2 (reconstruction,
  *     smoothness indicators, scale-invariant nonlinear weights, moment
- *     modification) and the semi-discrete schemes Eq. (2.4) / (2.18) with
+ *     modification) and the semi-discrete schemes Eq. (2.3) / (2.16) with
  *     Lax-Friedrichs fluxes;
- *   - time discretisation: the modified SSP-RK3 of Eq. (2.11) (Step 4), which
+ *   - time discretisation: the modified SSP-RK3 of Eq. (2.13) (Step 4), which
  *     uses the modified moments v^ (w^) in the Runge-Kutta bases;
- *   - Euler equations: local characteristic decomposition (Remark 2.1).
+ *   - Euler equations: local characteristic decomposition (Remark 2.2).
  *
  * Memory model.  All state arrays are device memory owned by the caller.
  * Several independent instances may share one handle; instance k occupies
@@ -55,7 +55,7 @@ enum {
 
 enum { HWENOU_EQ_ADVECTION = 0, HWENOU_EQ_BURGERS = 1, HWENOU_EQ_EULER = 2 };
 enum { HWENOU_FP64 = 0, HWENOU_MIXED = 1 };
-/* nonlinear weights: scale-invariant (Eq. (2.8)/(2.14)), the scale-dependent
+/* nonlinear weights: scale-invariant (Eq. (2.11)/(2.22)), the scale-dependent
  * original (u_ave = 1, Remark 2.1 of Section 2.1), or linear (w = gamma). */
 enum { HWENOU_W_SCALE_INVARIANT = 0, HWENOU_W_ZQ = 1, HWENOU_W_LINEAR = 2 };
 /* Euler reconstruction variables (the local characteristic decomposition of
@@ -139,7 +139,7 @@ const char* hwenou_strerror(int code);
  * average is reported by the next hwenou_advance or hwenou_status call. */
 int hwenou_max_wavespeed(hwenou_handle* h, const double* ubar, double* alpha_dev);
 
-/* One fused stage s in {0, 1, 2} of the modified SSP-RK3 (Eq. (2.11)):
+/* One fused stage s in {0, 1, 2} of the modified SSP-RK3 (Eq. (2.13)):
  *   s = 0: out = (u, v^) + dt F(in)                 with (u, v^) from `in`
  *   s = 1: out = 3/4 (u^n, v^n) + 1/4 ((u, v^) + dt F(in))
  *   s = 2: out = 1/3 (u^n, v^n) + 2/3 ((u, v^) + dt F(in))

@@ -16,10 +16,10 @@ results are exact rationals:
   v4, v6, w2, w8, least squares on v2, v8, w4, w6 (constrained least
   squares, solved through its KKT system).  Linear p1..p4 from three averages
   each (stencils S1..S4 of the paper's Fig. 2.1).
-* Smoothness indicators (Eq. (2.7) in 1D, Eq. (2.12) in 2D) as Gram matrices
+* Smoothness indicators (Eq. (2.9) in 1D, Eq. (2.20) in 2D) as Gram matrices
   of the derivative integrals, in the normalised coordinates xi, eta.
 * q-functionals: first-order moments of a polynomial over the target cell
-  (the HWENO moment modification, Eq. (2.10) and (2.14)).
+  (the HWENO moment modification, Eq. (2.12) and (2.23)).
 
 Coordinates: xi = (x - x_i)/dx, eta = (y - y_j)/dy; the target cell is
 [-1/2, 1/2] (x [-1/2, 1/2]); neighbour k sits at offset k.

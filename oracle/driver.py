@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
 CPU-baseline leg of the benchmark import this module.  It loads the plain-C
 oracle (hwenou_oracle.c), hands it the operators derived exactly in
 derive.py, and performs the modified SSP Runge-Kutta combination of
-Eq. (2.11) (Section 2.1, Step 4; used unchanged in 2D, Section 2.2, Step 4):
+Eq. (2.13) (Section 2.1, Step 4; used unchanged in 2D, Section 2.2, Step 4):
 
   stage 0:  U1    = (u^n, v^n_hat) + dt F(U^n)
   stage 1:  U2    = 3/4 (u^n, v^n_hat) + 1/4 ((u1, v1_hat) + dt F(U1))

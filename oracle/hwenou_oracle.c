@@ -13,13 +13,13 @@
  * Hermite WENO scheme with unified stencils for hyperbolic conservation
  * laws", cell by cell, with plain loops:
  *   Step 1  polynomials p0 (quartic) and p_m (linear)         -- Sec. 2.1 / 2.2
- *   Step 2  smoothness indicators beta_m = c^T G c            -- Eq. (2.7)/(2.12)
- *   Step 3  tau, u_ave, scale-invariant nonlinear weights     -- Eq. (2.8)/(2.14)
- *           reconstruction u_i(x) and moment modification v^ -- Eq. (2.10)/(2.15)
- *   semi-discrete right-hand sides with Lax-Friedrichs fluxes -- Eq. (2.4)/(2.18)
- * The Runge-Kutta combination (Eq. (2.11)) is done by the Python driver.
+ *   Step 2  smoothness indicators beta_m = c^T G c            -- Eq. (2.9)/(2.20)
+ *   Step 3  tau, u_ave, scale-invariant nonlinear weights     -- Eq. (2.10)-(2.11)/(2.21)-(2.22)
+ *           reconstruction u_i(x) and moment modification v^ -- Eq. (2.12)/(2.23)
+ *   semi-discrete right-hand sides with Lax-Friedrichs fluxes -- Eq. (2.3)-(2.4)/(2.16)
+ * The Runge-Kutta combination (Eq. (2.13)) is done by the Python driver.
  * For the Euler equations the reconstruction runs on local characteristic
- * variables (Remark 2.1), projected with the eigenvectors of the flux
+ * variables (Remark 2.2), projected with the eigenvectors of the flux
  * Jacobian at the target cell's average; in 2D an x-sweep (eigenvectors of
  * f') yields the x-edge values, the interior values used for f and v^, and a
  * y-sweep (eigenvectors of g') the y-edge values, the interior values used

@@ -7,12 +7,12 @@
 //     Appendix tables, with the 2D c_{0,4} u_1 entry taken as -7/22 (the
 //     value the moment conditions give; the printed +7/22 breaks the
 //     antisymmetry of the xi*eta coefficient under x -> -x);
-//   * smoothness indicators: Eq. (2.7) in 1D with the first square read as
-//     (c_{0,1} + c_{0,3}/4)^2, and the printed sum of squares of Eq. (2.12) in 2D;
-//   * scale-invariant nonlinear weights, Eq. (2.8) / (2.14);
-//   * reconstruction u_i(x) and the HWENO moment modification, Eq. (2.10) / (2.15),
+//   * smoothness indicators: Eq. (2.9) in 1D with the first square read as
+//     (c_{0,1} + c_{0,3}/4)^2, and the printed sum of squares of Eq. (2.20) in 2D;
+//   * scale-invariant nonlinear weights, Eq. (2.10)-(2.11) / (2.21)-(2.22);
+//   * reconstruction u_i(x) and the HWENO moment modification, Eq. (2.12) / (2.23),
 //     written as one combined polynomial C = (w0/g0) p0 + sum_m (w_m - w0 g_m/g0) p_m;
-//   * Lax-Friedrichs fluxes and Euler eigenvectors (Remark 2.1).
+//   * Lax-Friedrichs fluxes (Eq. (2.4)) and Euler eigenvectors (Remark 2.2).
 // The types are templated so that the FP64 path and the mixed path (FP64
 // coefficients / smoothness indicators / weights, FP32 point values and
 // fluxes) share one code path.

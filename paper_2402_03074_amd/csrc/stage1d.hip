@@ -1,7 +1,7 @@
 // One fused HWENO-U Runge-Kutta stage in 1D (Section 2.1): reconstruction
 // (Steps 1-3), moment modification, Lax-Friedrichs fluxes, the semi-discrete
-// right-hand sides of Eq. (2.4) and the modified SSP-RK3 combination of
-// Eq. (2.11), for scalar laws and the Euler equations.
+// right-hand sides of Eq. (2.3) and the modified SSP-RK3 combination of
+// Eq. (2.13), for scalar laws and the Euler equations.
 //
 // Mapping: one wave per 62-cell tile.  Lane l reconstructs cell start-1+l;
 // lanes 1..62 own the output cells, lanes 0 and 63 only supply the interface

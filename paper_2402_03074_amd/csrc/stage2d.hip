@@ -2,11 +2,11 @@
 // quartic reconstruction on the 3x3 stencil (Step 1), smoothness indicators
 // and scale-invariant weights (Steps 2-3), the modified moments v^, w^, the
 // 21 point values, Lax-Friedrichs fluxes at the 3 Gauss points of every
-// edge, the right-hand sides F1, F2, F3 of Eq. (2.18) and the modified
+// edge, the right-hand sides F1, F2, F3 of Eq. (2.16) and the modified
 // SSP-RK3 update (Step 4).
 //
 // Euler: the reconstruction runs on local characteristic variables in two
-// direction-split sweeps (Remark 2.1).  The y-sweep projects the stencil with
+// direction-split sweeps (Remark 2.2).  The y-sweep projects the stencil with
 // the eigenvectors of g' at the cell average and yields the y-edge values,
 // the interior values used for g, and w^; the x-sweep does the same with f'
 // for the x-edges, f and v^.  Each characteristic field is reconstructed

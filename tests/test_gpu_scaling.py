@@ -5,7 +5,7 @@ velocities, the sound speed and so the eigenvectors, the wave speeds and the
 time step unchanged.  The characteristic variables and every point value,
 flux and update then scale by zeta.  The smoothness indicators and u_ave
 scale by zeta^2, and tau and beta_m u_ave by zeta^4.  So the weights of
-Eq. (2.8)/(2.14) are unchanged when eps scales by zeta^4 as well: this is
+Eq. (2.11)/(2.22) are unchanged when eps scales by zeta^4 as well: this is
 the scale invariance the weights are designed for.  With zeta a power of two,
 every rounding commutes with the scaling, so one step with the state scaled
 by zeta and eps by zeta^4 must give exactly zeta times the unscaled step.

@@ -225,14 +225,14 @@ def test_stability_bound_of_modified_rk3():
     bound = float([r for r in _rows("linear_scheme.txt") if r[0] == "CFL"][0][1])
     assert _max_radius(bound - 0.005) <= 1 + 1e-10
     assert _max_radius(bound + 0.01) > 1 + 1e-4
-    # Theorem 1: without the moment modification the scheme is unstable
+    # Theorem 2.1: without the moment modification the scheme is unstable
     assert _max_radius(0.01, modified=False, nK=400) > 1.01
     assert _max_radius(0.1, modified=False, nK=400) > 1.3
 
 
 def test_oracle_full_step_equals_amplification_matrix():
     """Linear weights, a = 1, periodic: n oracle RK steps on a Fourier mode
-    equal G3^n from the printed matrices (closed form, Theorem 2)."""
+    equal G3^n from the printed matrices (closed form, Theorem 2.2)."""
     n = 16
     P = Problem(1, "advection", n, (0.0, 2.0), weights="linear", adv=(1.0,))
     dx = 2.0 / n
@@ -359,7 +359,7 @@ def test_2d_exact_on_quartics():
 
 def test_zero_averages_give_linear_weights():
     """u_{i-1} = u_i = u_{i+1} = 0 makes u_ave = 0 and the weights linear
-    (Remark after Eq. (2.8)): the same output as the linear-weight oracle."""
+    (Remark 2.1, after Eq. (2.11)): the same output as the linear-weight oracle."""
     n = 10
     rng = np.random.default_rng(3)
     u = np.zeros((1, n))
@@ -734,7 +734,7 @@ def test_2d_accuracy_tables_coarsest_meshes():
 
 def test_theorem1_unmodified_scheme_blows_up():
     """Using v instead of v^ in the Runge-Kutta bases (the unmodified SSP-RK3
-    of Theorem 1) is unstable even at CFL 0.1; the modified scheme is not."""
+    of Theorem 2.1) is unstable even at CFL 0.1; the modified scheme is not."""
     n = 32
     P = Problem(1, "advection", n, (0, 2), adv=(1.0,), weights="linear")
     rng = np.random.default_rng(5)
