@@ -39,17 +39,6 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
   constexpr double rb = ST == 0 ? 1.0 : (ST == 1 ? 0.25 : 2.0 / 3.0);
   const long long plane = A.plane;
 
-  // wave speeds of the last stage: the maximum over the wave's consecutive
-  // tiles of one instance, committed with one atomic when the instance
-  // changes and at the end
-  int acc_inst = -1;
-  double acc = 0.0;
-  auto commit = [&]() {
-    if (ST == 2 && A.alpha_next != nullptr && acc_inst >= 0) {
-      const double mx = wave_max(acc);
-      if (lane == 0) atomic_max_nonneg(A.alpha_next + alpha_slot(acc_inst, blockIdx.x), mx);
-    }
-  };
   for (int it = A.work_ptr[w]; it < A.work_ptr[w + 1]; ++it) {
     const WorkItem wk = A.work[it];
     if (A.done != nullptr && A.done[wk.inst]) continue;
@@ -260,15 +249,10 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
     }
     if (!ok) atomicOr(&A.status[wk.inst], 1);
     if (ST == 2 && A.alpha_next != nullptr) {
-      if (wk.inst != acc_inst) {
-        commit();
-        acc_inst = wk.inst;
-        acc = 0.0;
-      }
-      acc = fmax(acc, owner ? sx : 0.0);
+      const double mx = wave_max(owner ? sx : 0.0);
+      if (lane == 0) atomic_max_nonneg(A.alpha_next + alpha_slot(wk.inst, blockIdx.x), mx);
     }
   }
-  commit();
 }
 
 template <int EQ, bool CHAR, class TR, class TM>
