@@ -64,6 +64,7 @@ struct hwenou_handle {
   // work lists
   int waves_per_cu = 0, rows_per_item = 0;
   int n_cu = 256;
+  int n_xcd = 8;  // chiplets, each with its own L2
   WorkItem* d_work = nullptr;
   int* d_work_ptr = nullptr;
   int n_waves = 0;
@@ -131,6 +132,36 @@ void free_handle(hwenou_handle* h) {
 //      strip-rows are split into equal runs, one per wave, so every wave
 //      marches about the same number of rows (a run that crosses the end of
 //      a strip continues at the bottom of the next one).
+// Order the waves' runs for the chiplets.  The hardware hands the blocks of a
+// launch to the XCDs in turn (block b to XCD b mod n_xcd), and every XCD has
+// an L2 of its own.  The runs are listed strip by strip, so a contiguous
+// range of the list holds a few whole neighbouring strips, and the waves of
+// two neighbouring strips that cover the same rows start together and march
+// in step.  Each XCD receives one contiguous range, so that the columns two
+// neighbouring strips both read (the two-column halos and the cache lines a
+// row segment straddles) are fetched from HBM once, into the L2 that both
+// waves read, instead of once per XCD.
+void xcd_order(std::vector<WorkItem>& items, std::vector<int>& ptr, int n_xcd) {
+  const int nw = (int)ptr.size() - 1;
+  if (n_xcd <= 1 || nw <= n_xcd) return;
+  std::vector<int> run_of_block(nw);
+  int r = 0;
+  for (int x = 0; x < n_xcd; ++x)
+    for (int b = x; b < nw; b += n_xcd) run_of_block[b] = r++;
+  std::vector<WorkItem> it2;
+  std::vector<int> p2;
+  it2.reserve(items.size());
+  p2.reserve(ptr.size());
+  p2.push_back(0);
+  for (int b = 0; b < nw; ++b) {
+    const int q = run_of_block[b];
+    for (int i = ptr[q]; i < ptr[q + 1]; ++i) it2.push_back(items[i]);
+    p2.push_back((int)it2.size());
+  }
+  items.swap(it2);
+  ptr.swap(p2);
+}
+
 int build_work(hwenou_handle* h) {
   drop_graph(h);  // the captured step graph holds the old work lists
   std::vector<WorkItem> items;
@@ -159,6 +190,24 @@ int build_work(hwenou_handle* h) {
       ptr.push_back((int)b);
     }
     items = tiles;
+  } else if (h->n_inst == 1 && h->rows_per_item <= 0) {
+    // One grid: every strip is cut at the same rows into `q` runs of near-
+    // equal length, and the runs are listed band by band.  The waves of one
+    // band start together at the same row and march in step, so neighbouring
+    // strips read their shared columns at the same time.
+    const int ny = h->inst[0].ny;
+    const int ns = (h->inst[0].nx + kStripWidth - 1) / kStripWidth;
+    long long q = std::max<long long>(1, target_waves / ns);
+    q = std::min<long long>(q, std::max(1, ny / 4));  // at least 4 rows per run
+    ptr.push_back(0);
+    for (long long b = 0; b < q; ++b) {
+      const int r0 = (int)(ny * b / q), r1 = (int)(ny * (b + 1) / q);
+      for (int s = 0; s < ns; ++s) {
+        items.push_back({0, s, r0, r1});
+        ptr.push_back((int)items.size());
+      }
+    }
+    xcd_order(items, ptr, h->n_xcd);
   } else {
     struct Strip {
       int inst, strip, rows;
@@ -191,6 +240,7 @@ int build_work(hwenou_handle* h) {
       }
     }
     if (used > 0) ptr.push_back((int)items.size());
+    xcd_order(items, ptr, h->n_xcd);
   }
   h->n_waves = (int)ptr.size() - 1;
   if (h->d_work) (void)hipFree(h->d_work);
@@ -409,6 +459,11 @@ int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, voi
     return hip_fail(e, "hipGetDeviceProperties");
   }
   h->n_cu = prop.multiProcessorCount;
+  {
+    int nx = 0;
+    if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && nx > 0)
+      h->n_xcd = nx;
+  }
 
   std::vector<InstDev> di(n_inst);
   for (int k = 0; k < n_inst; ++k) di[k] = inst_dev(d, inst[k]);
