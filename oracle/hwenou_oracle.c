@@ -46,6 +46,13 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Loops over fewer values than this run on one thread: every cell is
+ * computed independently, so the results do not depend on the thread count,
+ * and small grids stepped thousands of times would spend their time in the
+ * start-up of parallel regions. */
+#define ORACLE_OMP_MIN 16384
+#define ORACLE_OMP_MIN_2D 256 /* cells: a 2D cell costs ~30 times a 1D value */
+
 #define EQ_ADVECTION 0
 #define EQ_BURGERS 1
 #define EQ_EULER 2
@@ -409,7 +416,7 @@ int oracle_rhs_1d(const oracle_params *P, int n, double dx, int bc_lo, int bc_hi
   double *pts = (double *)malloc(sizeof(double) * (size_t)ne * 4 * nc);
   double *vh = (double *)malloc(sizeof(double) * (size_t)ne * nc);
   int bad = 0;
-#pragma omp parallel for schedule(static) reduction(| : bad)
+#pragma omp parallel for schedule(static) reduction(| : bad) if (ne * nc >= ORACLE_OMP_MIN)
   for (int e = 0; e < ne; ++e) {
     int i = e - 1;
     int idx[3], mir[3];
@@ -466,7 +473,7 @@ int oracle_rhs_1d(const oracle_params *P, int n, double dx, int bc_lo, int bc_hi
   }
   /* interface fluxes fh[e] at x_{i+1/2}, i = e-1, e = 0..n */
   double *fh = (double *)malloc(sizeof(double) * (size_t)(n + 1) * nc);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n * nc >= ORACLE_OMP_MIN)
   for (int e = 0; e <= n; ++e) {
     const double *um = pts + (size_t)e * 4 * nc + 3 * nc;      /* cell e-1 at +1/2 */
     const double *up = pts + (size_t)(e + 1) * 4 * nc + 0 * nc; /* cell e at -1/2 */
@@ -476,7 +483,7 @@ int oracle_rhs_1d(const oracle_params *P, int n, double dx, int bc_lo, int bc_hi
     for (int k = 0; k < nc; ++k)
       fh[(size_t)e * nc + k] = 0.5 * (fm[k] + fp[k] - alpha * (up[k] - um[k]));
   }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n * nc >= ORACLE_OMP_MIN)
   for (int i = 0; i < n; ++i) {
     const double *fl = fh + (size_t)i * nc;       /* x_{i-1/2} */
     const double *fr = fh + (size_t)(i + 1) * nc; /* x_{i+1/2} */
@@ -651,7 +658,7 @@ int oracle_rhs_2d(const oracle_params *P, int nx, int ny, double dx, double dy, 
   cell2d *C = (cell2d *)calloc((size_t)ex * ey, sizeof(cell2d));
   int bad = 0;
   /* labels 1..9 -> offsets (a, b): label = 5 + a + 3 b */
-#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad) if (ex * ey >= ORACLE_OMP_MIN_2D)
   for (int ej = 0; ej < ey; ++ej) {
     for (int ei = 0; ei < ex; ++ei) {
       int i = ei - 1, j = ej - 1;
@@ -758,7 +765,7 @@ int oracle_rhs_2d(const oracle_params *P, int nx, int ny, double dx, double dy, 
     return ERR_NONPHYSICAL;
   }
   /* fluxes and right-hand sides */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nx * ny >= ORACLE_OMP_MIN_2D)
   for (int j = 0; j < ny; ++j) {
     for (int i = 0; i < nx; ++i) {
       const cell2d *c = C + (size_t)(j + 1) * ex + (i + 1);
