@@ -43,8 +43,11 @@ VALU_PEAK_TFLOPS = 78.6
 # finish kernel of one step, which also sets the next dt (rocprofv3 kernel
 # trace: ~4 us)
 AUX_US_PER_STEP = 4.0
+# the counters also depend on the work lists the host library builds (which
+# wave reads which rows and columns), so its source is hashed with the kernels
 COMMON_SOURCES = ["paper_2402_03074_amd/csrc/hwenou_device.hpp",
-                  "paper_2402_03074_amd/csrc/hwenou_internal.hpp"]
+                  "paper_2402_03074_amd/csrc/hwenou_internal.hpp",
+                  "paper_2402_03074_amd/csrc/hwenou_api.hip"]
 KERNEL_SOURCES = ["paper_2402_03074_amd/csrc/stage2d.hip"] + COMMON_SOURCES
 # rocprofv3 counter summaries (profiles/) per stage kernel and the workload
 # they were taken on

@@ -86,14 +86,14 @@ def test_2d_vortex_mixed_matches_fp64_l1_error():
 
 def test_2d_vortex_projection_modes():
     """Cost/accuracy of the reconstruction variables on the smooth vortex
-    (FP64): the single x-projection and the component-wise reconstruction
-    keep the error of the direction-split characteristic scheme within a
-    factor 1.5 and converge at least at third order (the time error) between
-    64^2 and 128^2."""
+    (FP64): the single x-projection, the component-wise reconstruction and
+    the per-interface bases keep the error of the direction-split
+    characteristic scheme within a factor 1.5 and converge at least at third
+    order (the time error) between 64^2 and 128^2."""
     print("[gpu] 2D vortex, projection modes", flush=True)
-    e = {(c, n): _vortex_l1(n, 1.0, "fp64", c) for c in (1, 2, 0) for n in (64, 128)}
+    e = {(c, n): _vortex_l1(n, 1.0, "fp64", c) for c in (1, 2, 0, 3) for n in (64, 128)}
     print({k: f"{v:.4e}" for k, v in e.items()}, flush=True)
-    for c in (2, 0):
+    for c in (2, 0, 3):
         for n in (64, 128):
             assert e[(c, n)] <= 1.5 * e[(1, n)]
         assert e[(c, 64)] / e[(c, 128)] > 8.0
