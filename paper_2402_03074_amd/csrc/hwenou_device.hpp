@@ -411,6 +411,34 @@ __device__ __forceinline__ void restrict_xi(const TR (&C)[15], TR e, TR (&d)[5])
   d[3] = C[9] + e * C[13];
   d[4] = C[14];
 }
+// The same restrictions to the three Gauss lines g = 0, 1, 2 at -sqrt15/10,
+// 0, +sqrt15/10: on the middle line the restriction is a selection of
+// coefficients.  (The general form would multiply by zero there, which the
+// compiler must keep, since 0 * x is not 0 for every x.)
+template <class TR>
+__device__ __forceinline__ void restrict_eta_line(const TR (&C)[15], int g, TR (&d)[5]) {
+  if (g == 1) {
+    d[0] = C[0];
+    d[1] = C[1];
+    d[2] = C[3];
+    d[3] = C[6];
+    d[4] = C[10];
+  } else {
+    restrict_eta<TR>(C, g == 0 ? (TR)-G3S : (TR)G3S, d);
+  }
+}
+template <class TR>
+__device__ __forceinline__ void restrict_xi_line(const TR (&C)[15], int g, TR (&d)[5]) {
+  if (g == 1) {
+    d[0] = C[0];
+    d[1] = C[2];
+    d[2] = C[5];
+    d[3] = C[9];
+    d[4] = C[14];
+  } else {
+    restrict_xi<TR>(C, g == 0 ? (TR)-G3S : (TR)G3S, d);
+  }
+}
 // 1D quartic d at +-1/2 (edges) and +-sqrt15/10, 0 (Gauss points)
 template <class TR>
 __device__ __forceinline__ void eval5(const TR (&d)[5], TR& em, TR& ep, TR& gm, TR& g0, TR& gp) {

@@ -488,7 +488,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             TR d[5], e0, e1, g0, g1, g2;
-            restrict_xi<TR>(Cc[k], (TR)g3x(G), d);
+            restrict_xi_line<TR>(Cc[k], G, d);
             eval5<TR>(d, e0, e1, g0, g1, g2);
             ebuf[(3 + G) * NC + k][lane] = e1;
           }
@@ -502,7 +502,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
               TR d[5], e0, e1, g0, g1, g2;
-              restrict_xi<TR>(Cc[k], (TR)g3x(G), d);
+              restrict_xi_line<TR>(Cc[k], G, d);
               eval5<TR>(d, e0, e1, g0, g1, g2);
               ebuf[G * NC + k][lane] = e0;
             }
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
           TR d[5];
-          restrict_xi<TR>(Cc[k], xg, d);
+          restrict_xi_line<TR>(Cc[k], G, d);
           eval5<TR>(d, ym[k], yp[k], in[0][k], in[1][k], in[2][k]);
           if constexpr (IFACE) {
             ym[k] = ebuf[G * NC + k][lane];
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             F1n_s[k] += wg * gb[k];       // sum_G w_G g_{G,j-1/2}
-            F2n[k] += wg * xg * gb[k];    // sum_G w_G xi_G g_{G,j-1/2}
+            if (G != 1) F2n[k] += wg * xg * gb[k];  // sum_G w_G xi_G g_{G,j-1/2} (xi_1 = 0)
           }
         }
 #pragma unroll
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
               TR d[5], e0, e1, g0, g1, g2;
-              restrict_eta<TR>(Cc[k], (TR)g3x(H), d);
+              restrict_eta_line<TR>(Cc[k], H, d);
               eval5<TR>(d, e0, e1, g0, g1, g2);
               ebuf[H * NC + k][lane] = e0;
             }
@@ -672,7 +672,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
               TR d[5], e0, e1, g0, g1, g2;
-              restrict_eta<TR>(Cc[k], (TR)g3x(H), d);
+              restrict_eta_line<TR>(Cc[k], H, d);
               eval5<TR>(d, e0, e1, g0, g1, g2);
               ebuf[(3 + H) * NC + k][lane] = e1;
             }
@@ -698,7 +698,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 #pragma unroll
           for (int k = 0; k < NC; ++k) {
             TR d[5];
-            restrict_eta<TR>(Cc[k], yh, d);
+            restrict_eta_line<TR>(Cc[k], H, d);
             eval5<TR>(d, xm[k], xp[k], in[0][k], in[1][k], in[2][k]);
             if constexpr (IFACE) {
               xm[k] = ebuf[H * NC + k][lane];
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
           for (int k = 0; k < NC; ++k) {
             F1x[k] += (double)wg * ((double)fr[k] - (double)fl[k]);
             F2x[k] += wg * (fl[k] + fr[k]);
-            F3x[k] += wg * yh * (fr[k] - fl[k]);
+            if (H != 1) F3x[k] += wg * yh * (fr[k] - fl[k]);  // eta_1 = 0
           }
         }
         // pending right-hand side of row j
