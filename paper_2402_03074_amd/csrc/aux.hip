@@ -94,8 +94,10 @@ __device__ void set_step(const AuxArgs& A, int k) {
 // Before the first step: its time step, and the reset of the wave-speed
 // accumulators that the last stage of the step fills.
 __global__ __launch_bounds__(256) void dt_kernel(const AuxArgs A) {
-  for (int k = threadIdx.x; k < A.n_inst * kAlphaSlots * 2; k += blockDim.x)
-    A.alpha_next[k] = 0.0;
+  for (int k = threadIdx.x; k < A.n_inst * A.alpha_slots; k += blockDim.x) {
+    A.alpha_next[kAlphaStride * k] = 0.0;
+    A.alpha_next[kAlphaStride * k + 1] = 0.0;
+  }
   for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) set_step(A, k);
 }
 
@@ -108,19 +110,36 @@ __global__ __launch_bounds__(256) void finish_kernel(const AuxArgs A) {
   __syncthreads();
   int mine = 0;
   for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) {
-    double* acc = A.alpha_next + 2 * kAlphaSlots * k;
+    double* acc = A.alpha_next + alpha_slot(k, 0, A.alpha_slots);
     if (!A.done[k]) {
       A.t[k] += A.dt[k];
       A.steps[k] += 1;
-      double ax = acc[0], ay = acc[1];
+      // every slot line of the allocation is loaded at once (in bounds: the
+      // array holds kAlphaSlots lines per instance), and those beyond this
+      // instance's slots count as zero (the wave speeds are non-negative)
+      double sx[kAlphaSlots], sy[kAlphaSlots];
+#pragma unroll
+      for (int s = 0; s < kAlphaSlots; ++s) {
+        sx[s] = acc[kAlphaStride * s];
+        sy[s] = acc[kAlphaStride * s + 1];
+      }
+      double ax = sx[0], ay = sy[0];
+#pragma unroll
       for (int s = 1; s < kAlphaSlots; ++s) {
-        ax = fmax(ax, acc[2 * s]);
-        ay = fmax(ay, acc[2 * s + 1]);
+        const bool mine = s < A.alpha_slots;
+        ax = fmax(ax, mine ? sx[s] : 0.0);
+        ay = fmax(ay, mine ? sy[s] : 0.0);
       }
       A.alpha[2 * k] = ax;
       A.alpha[2 * k + 1] = ay;
     }
-    for (int s = 0; s < 2 * kAlphaSlots; ++s) acc[s] = 0.0;
+#pragma unroll
+    for (int s = 0; s < kAlphaSlots; ++s) {
+      if (s < A.alpha_slots) {
+        acc[kAlphaStride * s] = 0.0;
+        acc[kAlphaStride * s + 1] = 0.0;
+      }
+    }
     set_step(A, k);
     if (!A.done[k]) mine = 1;
   }

@@ -65,6 +65,7 @@ struct hwenou_handle {
   int waves_per_cu = 0, rows_per_item = 0;
   int n_cu = 256;
   int n_xcd = 8;  // chiplets, each with its own L2
+  int alpha_slots = 1;  // wave-speed accumulators per instance
   WorkItem* d_work = nullptr;
   int* d_work_ptr = nullptr;
   int n_waves = 0;
@@ -243,6 +244,22 @@ int build_work(hwenou_handle* h) {
     xcd_order(items, ptr, h->n_xcd);
   }
   h->n_waves = (int)ptr.size() - 1;
+  {
+    // waves per instance, for the number of wave-speed accumulators
+    std::vector<int> waves(h->n_inst, 0), last(h->n_inst, -1);
+    for (int w = 0; w < h->n_waves; ++w)
+      for (int i = ptr[w]; i < ptr[w + 1]; ++i) {
+        const int k = items[i].inst;
+        if (last[k] != w) {
+          last[k] = w;
+          ++waves[k];
+        }
+      }
+    const int busiest = waves.empty() ? 0 : *std::max_element(waves.begin(), waves.end());
+    int slots = 1;
+    while (slots < kAlphaSlots && 64 * slots < busiest) slots *= 2;
+    h->alpha_slots = slots;
+  }
   if (h->d_work) (void)hipFree(h->d_work);
   if (h->d_work_ptr) (void)hipFree(h->d_work_ptr);
   h->d_work = nullptr;
@@ -277,6 +294,11 @@ namespace {
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// Wave-speed accumulators per instance (set with the work lists): one per
+// 64 waves that work on the busiest instance, a power of two from 1 to
+// kAlphaSlots.
+int alpha_slots(const hwenou_handle* h) { return h->alpha_slots; }
+
 int launch_stage(hwenou_handle* h, int s, const double* dt, const double* alpha, const int* done,
                  const double* u_in, const void* m_in, double* u_out, void* m_out,
                  double* alpha_next, hipStream_t st) {
@@ -301,6 +323,7 @@ int launch_stage(hwenou_handle* h, int s, const double* dt, const double* alpha,
     A.u_out = u_out;
     A.m_out = mo;
     A.alpha_next = alpha_next;
+    A.alpha_slots = alpha_slots(h);
     A.status = h->d_status;
     A.plane = h->plane;
     A.work = h->d_work;
@@ -345,6 +368,7 @@ AuxArgs aux_args(hwenou_handle* h, const double* u) {
   a.done = h->d_done;
   a.status = h->d_status;
   a.alpha_next = h->d_alpha_next;
+  a.alpha_slots = alpha_slots(h);
   a.run = h->d_run;
   a.all_done = h->d_all_done;
   return a;
@@ -479,7 +503,7 @@ int hwenou_create(const hwenou_desc* d, int n_inst, const hwenou_inst* inst, voi
   } while (0)
   TRY(dalloc(&h->d_inst, n_inst));
   TRY(dalloc(&h->d_alpha, 2 * n_inst));
-  TRY(dalloc(&h->d_alpha_next, 2 * kAlphaSlots * n_inst));
+  TRY(dalloc(&h->d_alpha_next, (size_t)kAlphaStride * kAlphaSlots * n_inst));
   TRY(dalloc(&h->d_dt, n_inst));
   TRY(dalloc(&h->d_t, n_inst));
   TRY(dalloc(&h->d_steps, n_inst));

@@ -27,13 +27,19 @@ struct WorkItem {
 // the neighbouring cells whose interface values the strip needs.
 constexpr int kStripWidth = 62;
 
-// The last stage reduces the wave speeds of its output into kAlphaSlots
-// accumulators per instance and direction (the wave's block index picks
-// one), so that ~1000 waves ending together do not all serialise their
-// atomics on one address; the finish kernel takes the maximum of the slots.
-constexpr int kAlphaSlots = 8;
-__device__ __forceinline__ int alpha_slot(int inst, int block) {
-  return 2 * (inst * kAlphaSlots + (block & (kAlphaSlots - 1)));
+// The last stage reduces the wave speeds of its output into `slots`
+// accumulators per instance (a power of two up to kAlphaSlots; the wave's
+// index picks one), so that ~1000 waves ending together on one instance do
+// not all serialise their atomics on one address.  Each accumulator (x and y
+// wave speed) sits in a 128-byte line of its own (kAlphaStride doubles),
+// since the atomics of one line are serialised as well; the finish kernel
+// takes the maximum of the slots.  Handles of many instances use fewer slots
+// per instance: few waves end on any one instance at a time, and the finish
+// kernel's loop over the slots grows with their number.
+constexpr int kAlphaSlots = 16;
+constexpr int kAlphaStride = 16;
+__device__ __host__ __forceinline__ int alpha_slot(int inst, int wave, int slots) {
+  return kAlphaStride * (inst * slots + (wave & (slots - 1)));
 }
 
 template <class TM>
@@ -49,7 +55,9 @@ struct StageArgs {
   TM* m_base;           // v^_n (and w^_n): written by stage 0, read by stages 1, 2
   double* u_out;
   TM* m_out;
-  double* alpha_next;   // [n_inst][kAlphaSlots][2] or nullptr: max wave speed of the output
+  double* alpha_next;   // [n_inst][alpha_slots][kAlphaStride] or nullptr: max wave speed of
+                        // the output (x, y in the first two doubles of each slot)
+  int alpha_slots;      // accumulators per instance (power of two, <= kAlphaSlots)
   int* status;          // [n_inst]: set to 1 on a non-physical or non-finite output
   long long plane;      // cells per component plane
   const WorkItem* work;
@@ -101,7 +109,8 @@ struct AuxArgs {
   int* steps;            // [n_inst]
   int* done;             // [n_inst]
   int* status;           // [n_inst]: 1 once the instance left the physical states
-  double* alpha_next;    // [n_inst][kAlphaSlots][2]
+  double* alpha_next;    // [n_inst][alpha_slots][kAlphaStride]
+  int alpha_slots;
   const RunParams* run;  // CFL number, final time, step limit
   int* all_done;         // 1 when every instance is done
 };

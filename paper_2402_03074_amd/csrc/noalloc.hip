@@ -177,6 +177,7 @@ extern "C" int hwenou_step_noalloc(const hwenou_desc* d, const hwenou_inst* inst
     A.u_base = ubar;
     A.m_base = static_cast<TM*>(m_base);
     A.alpha_next = nullptr;
+    A.alpha_slots = 1;
     A.status = status;
     A.plane = cells;
     A.work = reinterpret_cast<const WorkItem*>(base + off_items);

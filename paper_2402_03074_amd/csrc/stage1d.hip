@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
     if (!ok) atomicOr(&A.status[wk.inst], 1);
     if (ST == 2 && A.alpha_next != nullptr) {
       const double mx = wave_max(owner ? sx : 0.0);
-      if (lane == 0) atomic_max_nonneg(A.alpha_next + alpha_slot(wk.inst, blockIdx.x), mx);
+      if (lane == 0) atomic_max_nonneg(A.alpha_next + alpha_slot(wk.inst, w, A.alpha_slots), mx);
     }
   }
 }

@@ -755,7 +755,7 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
     if (ST == 2 && A.alpha_next != nullptr) {
       const double mx = wave_max(amax_x), my = wave_max(amax_y);
       if (lane == 0) {
-        double* acc = A.alpha_next + alpha_slot(wk.inst, blockIdx.x);
+        double* acc = A.alpha_next + alpha_slot(wk.inst, blockIdx.x, A.alpha_slots);
         atomic_max_nonneg(acc, mx);
         atomic_max_nonneg(acc + 1, my);
       }
