@@ -55,30 +55,29 @@ hipError_t launch_max_wavespeed(const AuxArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Time step of instance k for the step that starts at its current t, from
-// its current alpha; marks the instance done when it has reached t_final or
-// max_steps, or when a kernel has flagged one of its states as non-physical
-// or non-finite (dt = 0 then: the instance stops at the step that failed,
-// and its t and step count say where).  The wave speeds are reduced with
-// fmax, which drops NaN arguments, so a NaN state is caught by the flag, not
-// by alpha.
-__device__ void set_step(const AuxArgs& A, int k) {
-  const InstDev I = A.inst[k];
-  const double t = A.t[k];
-  const RunParams R = *A.run;
-  const bool finished = A.done[k] || A.steps[k] >= R.max_steps ||
-                        t >= R.t_final * (1.0 - 1e-14);
-  if (finished || A.status[k]) {
+// Time step of instance k for the step that starts at time t after `steps`
+// steps, from its wave speeds (ax, ay); marks the instance done when it has
+// reached t_final or max_steps, or when a kernel has flagged one of its
+// states as non-physical or non-finite (dt = 0 then: the instance stops at
+// the step that failed, and its t and step count say where).  The wave
+// speeds are reduced with fmax, which drops NaN arguments, so a NaN state is
+// caught by the flag, not by alpha.  The caller passes the values it has
+// loaded, so that each step's bookkeeping costs one round of loads.  Returns
+// whether the instance is done.
+__device__ bool set_step(const AuxArgs& A, int k, const InstDev& I, const RunParams& R, bool done,
+                         double t, int steps, int status, double ax, double ay) {
+  const bool finished = done || steps >= R.max_steps || t >= R.t_final * (1.0 - 1e-14);
+  if (finished || status) {
     A.done[k] = 1;
     A.dt[k] = 0.0;
-    return;
+    return true;
   }
-  const double ax = A.alpha[2 * k], ay = A.dim == 1 ? 0.0 : A.alpha[2 * k + 1];
+  if (A.dim == 1) ay = 0.0;
   if (!isfinite(ax) || !isfinite(ay)) {  // infinite wave speed: stop and report it
     A.done[k] = 1;
     A.dt[k] = 0.0;
     atomicOr(&A.status[k], 1);
-    return;
+    return true;
   }
   double dt;
   if (ax == 0.0 && ay == 0.0)
@@ -89,6 +88,7 @@ __device__ void set_step(const AuxArgs& A, int k) {
     dt = R.cfl / (ax / I.dx + ay / I.dy);
   if (t + dt > R.t_final) dt = R.t_final - t;
   A.dt[k] = dt;
+  return false;
 }
 
 // Before the first step: its time step, and the reset of the wave-speed
@@ -98,40 +98,56 @@ __global__ __launch_bounds__(256) void dt_kernel(const AuxArgs A) {
     A.alpha_next[kAlphaStride * k] = 0.0;
     A.alpha_next[kAlphaStride * k + 1] = 0.0;
   }
-  for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) set_step(A, k);
+  for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x)
+    set_step(A, k, A.inst[k], *A.run, A.done[k] != 0, A.t[k], A.steps[k], A.status[k],
+             A.alpha[2 * k], A.alpha[2 * k + 1]);
 }
 
 // End of a step: advance t and the step count, take the new wave speed,
 // reset its accumulator, set the next step's time step, and count the
-// instances still running (read by the host every few steps).
+// instances still running (read by the host every few steps).  Everything
+// an instance needs is loaded up front, in one round of loads.
 __global__ __launch_bounds__(256) void finish_kernel(const AuxArgs A) {
   __shared__ int running;
   if (threadIdx.x == 0) running = 0;
   __syncthreads();
   int mine = 0;
+  const RunParams R = *A.run;
   for (int k = threadIdx.x; k < A.n_inst; k += blockDim.x) {
     double* acc = A.alpha_next + alpha_slot(k, 0, A.alpha_slots);
-    if (!A.done[k]) {
-      A.t[k] += A.dt[k];
-      A.steps[k] += 1;
-      // every slot line of the allocation is loaded at once (in bounds: the
-      // array holds kAlphaSlots lines per instance), and those beyond this
-      // instance's slots count as zero (the wave speeds are non-negative)
-      double sx[kAlphaSlots], sy[kAlphaSlots];
+    const bool done = A.done[k] != 0;
+    double t = A.t[k];
+    const double dt = A.dt[k];
+    int steps = A.steps[k];
+    const int status = A.status[k];
+    const InstDev I = A.inst[k];
+    // every slot line of the allocation is loaded at once (in bounds: the
+    // array holds kAlphaSlots lines per instance), and those beyond this
+    // instance's slots count as zero (the wave speeds are non-negative)
+    double sx[kAlphaSlots], sy[kAlphaSlots];
 #pragma unroll
-      for (int s = 0; s < kAlphaSlots; ++s) {
-        sx[s] = acc[kAlphaStride * s];
-        sy[s] = acc[kAlphaStride * s + 1];
-      }
-      double ax = sx[0], ay = sy[0];
+    for (int s = 0; s < kAlphaSlots; ++s) {
+      sx[s] = acc[kAlphaStride * s];
+      sy[s] = acc[kAlphaStride * s + 1];
+    }
+    double ax, ay;
+    if (!done) {
+      t += dt;
+      steps += 1;
+      ax = sx[0];
+      ay = sy[0];
 #pragma unroll
       for (int s = 1; s < kAlphaSlots; ++s) {
-        const bool mine = s < A.alpha_slots;
-        ax = fmax(ax, mine ? sx[s] : 0.0);
-        ay = fmax(ay, mine ? sy[s] : 0.0);
+        const bool own = s < A.alpha_slots;
+        ax = fmax(ax, own ? sx[s] : 0.0);
+        ay = fmax(ay, own ? sy[s] : 0.0);
       }
+      A.t[k] = t;
+      A.steps[k] = steps;
       A.alpha[2 * k] = ax;
       A.alpha[2 * k + 1] = ay;
+    } else {
+      ax = ay = 0.0;  // unused: a done instance stays done
     }
 #pragma unroll
     for (int s = 0; s < kAlphaSlots; ++s) {
@@ -140,8 +156,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const AuxArgs A) {
         acc[kAlphaStride * s + 1] = 0.0;
       }
     }
-    set_step(A, k);
-    if (!A.done[k]) mine = 1;
+    if (!set_step(A, k, I, R, done, t, steps, status, ax, ay)) mine = 1;
   }
   if (mine) atomicOr(&running, 1);
   __syncthreads();
