@@ -191,8 +191,10 @@ int hwenou_status(hwenou_handle* h);
 
 /* Launch configuration of the stage kernels: waves per compute unit of the
  * persistent launch (1..32) and, in 2D, the rows a wave marches per work
- * item before the work list splits (0 = balanced automatically).  Used by
- * the autotuner; takes effect on the next call. */
+ * item before the work list splits (0 = automatic: a handle of one grid cuts
+ * every strip at the same rows and hands the runs to the chiplets in
+ * contiguous ranges; a handle of many instances balances equal runs).  Used
+ * by the autotuner; takes effect on the next call. */
 int hwenou_set_launch(hwenou_handle* h, int waves_per_cu, int rows_per_item);
 
 /* Autotuner of the persistent launch shape: times stage 0 on (ubar, mom)
