@@ -168,20 +168,22 @@ def test_batch_instances_finish_at_their_own_final_time():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("dim", [1, 2])
-def test_graph_replay_equals_eager_stages(dim, precision):
+@pytest.mark.parametrize("dim,big", [(1, False), (2, False), (1, True), (2, True)])
+def test_graph_replay_equals_eager_stages(dim, big, precision):
     """Graph replays take each step's alpha from the wave speeds that the
     stage-2 kernel reduces while it writes the step's result; the eager
     stages here take it from the separate max-wave-speed kernel.  Equal
-    states after 5 steps pin the fused reduction bitwise."""
-    print(f"[gpu] graph vs eager dim={dim} {precision}", flush=True)
+    states after 5 steps pin the fused reduction bitwise.  The small grids
+    reduce into one accumulator per instance; the big ones (about 1000 waves
+    on the one instance) into several, whose maximum the finish kernel takes."""
+    print(f"[gpu] graph vs eager dim={dim} big={big} {precision}", flush=True)
     if dim == 1:
-        n = 3000
+        n = 65536 if big else 3000
         u0, m0 = W.euler_1d_shocktube(n, seed=5201)
         P = Problem(1, "euler", n, (0, 1), bc="transmissive")
         dx = 1.0 / n
     else:
-        n = 96
+        n = 512 if big else 96
         u0, m0 = W.euler_2d_vortex_quadrant(n, seed=5200, q=2)
         P = Problem(2, "euler", (n, n), (0, 10, 0, 10))
         dx = 10.0 / n
