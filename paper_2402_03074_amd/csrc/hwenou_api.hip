@@ -127,21 +127,16 @@ void free_handle(hwenou_handle* h) {
   delete h;
 }
 
-// Build the per-wave work lists.
-//  1D: tiles of kStripWidth cells; tiles are dealt out in contiguous runs.
-//  2D: strips of kStripWidth columns, each a column of ny rows; the total
-//      strip-rows are split into equal runs, one per wave, so every wave
-//      marches about the same number of rows (a run that crosses the end of
-//      a strip continues at the bottom of the next one).
 // Order the waves' runs for the chiplets.  The hardware hands the blocks of a
 // launch to the XCDs in turn (block b to XCD b mod n_xcd), and every XCD has
-// an L2 of its own.  The runs are listed strip by strip, so a contiguous
-// range of the list holds a few whole neighbouring strips, and the waves of
-// two neighbouring strips that cover the same rows start together and march
-// in step.  Each XCD receives one contiguous range, so that the columns two
-// neighbouring strips both read (the two-column halos and the cache lines a
-// row segment straddles) are fetched from HBM once, into the L2 that both
-// waves read, instead of once per XCD.
+// an L2 of its own.  The 2D work lists put runs that read the same cache
+// lines next to each other (one grid: the strips of one band; many
+// instances: consecutive rows of a strip, then the neighbouring strip), and
+// here each XCD receives one contiguous range of the list.  For one grid the
+// waves of neighbouring strips in a band then start together, march in step
+// and share the columns at their common edge (the two-column halos and the
+// cache lines a row segment straddles) through one L2, which fetches them
+// from HBM once instead of once per XCD.
 void xcd_order(std::vector<WorkItem>& items, std::vector<int>& ptr, int n_xcd) {
   const int nw = (int)ptr.size() - 1;
   if (n_xcd <= 1 || nw <= n_xcd) return;
@@ -163,6 +158,15 @@ void xcd_order(std::vector<WorkItem>& items, std::vector<int>& ptr, int n_xcd) {
   ptr.swap(p2);
 }
 
+// Build the per-wave work lists.
+//  1D: tiles of kStripWidth cells; tiles are dealt out in contiguous runs.
+//  2D, one grid (automatic shape): strips of kStripWidth columns, every strip
+//      cut at the same rows into as many runs as fit the resident waves.
+//  2D otherwise: the total strip-rows of all instances are split into equal
+//      runs, one per wave, so every wave marches about the same number of
+//      rows (a run that crosses the end of a strip continues at the bottom of
+//      the next one).
+// Also sets the number of wave-speed accumulators per instance.
 int build_work(hwenou_handle* h) {
   drop_graph(h);  // the captured step graph holds the old work lists
   std::vector<WorkItem> items;
