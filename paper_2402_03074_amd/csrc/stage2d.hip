@@ -233,8 +233,10 @@ __device__ __forceinline__ void char_field(const SchemeParams& P, const Prim& pr
 // then into Cc.  The entropy field (K = 1) has the same left row and right
 // column in both directions: its polynomial is reconstructed once per cell
 // (by the first sweep) and passed to the second through LDS (PARK: a second
-// sweep follows).
-template <int DIR, bool SI, bool PARK, class TR, class TM>
+// sweep follows).  OVERLAP12: no scheduling barrier between fields 1 and 2
+// (the FP64 split sweeps fit their registers without it and run 0.7% faster;
+// the other kernels then spill or run slower).
+template <int DIR, bool SI, bool PARK, class TR, class TM, bool OVERLAP12 = false>
 __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr,
                                            const RowBuf<4, TM>& B, int sb, int sc, int st, int l,
                                            TR (&Cc)[4][15], TR (*c1buf)[64], bool have_c1) {
@@ -287,7 +289,7 @@ __device__ __forceinline__ void char_sweep(const SchemeParams& P, const Prim& pr
       Cc[3][n] = fh * C1[n] + (tunc * D[n] + tH * S[n]);
     }
   }
-  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (!OVERLAP12) __builtin_amdgcn_sched_barrier(0);
   char_field<DIR, 2, SI, TR, TM>(P, pr, B, sb, sc, st, l, C, a);
   {
     const TR tut = (TR)ut, a2 = (TR)a, uta2 = (TR)(ut * a);
@@ -519,8 +521,8 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) U5[k] = B.u[sc][k][lane + 1];
         pr = make_prim<TR>(gm1, U5);
-        char_sweep<SPLIT ? 1 : 0, SI, SPLIT, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf,
-                                                      false);
+        char_sweep<SPLIT ? 1 : 0, SI, SPLIT, TR, TM, SPLIT && sizeof(TR) == 8>(
+            P, pr, B, sb, sc, st, lane, Cc, c1buf, false);
       } else {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
@@ -683,7 +685,8 @@ __global__ __launch_bounds__(64, 1) void stage2d_kernel(const StageArgs<TM> A) {
           pr = make_prim<TR>(gm1, U5);
         }
         if constexpr (SPLIT)
-          char_sweep<0, SI, false, TR, TM>(P, pr, B, sb, sc, st, lane, Cc, c1buf, true);
+          char_sweep<0, SI, false, TR, TM, !IFACE && sizeof(TR) == 8>(P, pr, B, sb, sc, st, lane,
+                                                                      Cc, c1buf, true);
         double F1x[NC];
         TR F2x[NC], F3x[NC];
 #pragma unroll
