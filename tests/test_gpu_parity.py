@@ -221,7 +221,9 @@ def test_full_size_1d_euler_all_cells(precision):
                 assert l1 <= 1e-4, (steps, eu, em, l1)
             continue
         if steps == 1:
-            assert eu <= 10 * TOL_STAGE and em <= 10 * TOL_STAGE, (eu, em)
+            # a whole step (three stages) within the one-stage bar: measured
+            # 8e-16 / 4e-15
+            assert eu <= TOL_STAGE and em <= TOL_STAGE, (eu, em)
             continue
         rng = np.random.default_rng(1)
         up = u0 * (1 + 1e-16 * rng.standard_normal(u0.shape))
@@ -235,7 +237,8 @@ def test_full_size_1d_euler_all_cells(precision):
 
 def test_full_batch_1d_sampled_instances():
     """The 512-instance 1D batch in one handle: three instances compared with
-    the oracle after one step."""
+    the oracle after one step, averages and moments, within the one-stage bar
+    (measured 8e-16 / 4e-15)."""
     import torch
     import paper_2402_03074_amd as H
     print("[gpu] full 1D batch sampled parity", flush=True)
@@ -249,12 +252,13 @@ def test_full_batch_1d_sampled_instances():
     S = H.Solver(1, "euler", insts)
     ug, mg = to_gpu(u), to_gpu(m)
     S.advance(ug, mg, 0.6, 1e30, 1)
-    got = ug.cpu().numpy()
+    got, got_m = ug.cpu().numpy(), mg.cpu().numpy()
     for k in (0, 255, 511):
         a, b = insts[k].offset, insts[k].offset + insts[k].nx
         P = Problem(1, "euler", insts[k].nx, (0.0, 1.0), bc="transmissive")
         uo, mo, _, _ = P.advance(data[k][0], data[k][1], cfl=0.6, max_steps=1)
-        assert rel_err(got[:, a:b], uo, 1) <= TOL_STAGE * 10
+        eu, em = state_err(P, (got[:, a:b], got_m[:, :, a:b]), (uo, mo))
+        assert eu <= TOL_STAGE and em <= TOL_STAGE, (k, eu, em)
     S.close()
 
 
@@ -262,7 +266,8 @@ def test_full_batch_2d_sampled_instances():
     """The 64-instance 2D batch (grids of 256^2 to 1024^2, 22 M cells) in one
     handle, at the default launch shape (results do not depend on it, see
     test_launch_shape_invariance): one step, then the smallest, a median and
-    the largest instance compared whole with the oracle."""
+    the largest instance compared whole with the oracle, within the one-stage
+    bar (measured 1e-15 / 1e-14)."""
     import torch
     import paper_2402_03074_amd as H
     print("[gpu] full 2D batch sampled parity: generating", flush=True)
@@ -290,7 +295,7 @@ def test_full_batch_2d_sampled_instances():
         uo, mo, _, _ = P.advance(data[k][0], data[k][1], cfl=0.6, max_steps=1)
         got = (got_u[:, a:b].reshape(4, n, n), got_m[:, :, a:b].reshape(2, 4, n, n))
         eu, em = state_err(P, got, (uo, mo))
-        assert eu <= TOL_STAGE * 10 and em <= TOL_STAGE * 10, (k, n, eu, em)
+        assert eu <= TOL_STAGE and em <= TOL_STAGE, (k, n, eu, em)
 
 
 @pytest.mark.parametrize("weights", ["zq", "linear"])
