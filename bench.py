@@ -44,10 +44,12 @@ VALU_PEAK_TFLOPS = 78.6
 # trace: ~4 us)
 AUX_US_PER_STEP = 4.0
 # the counters also depend on the work lists the host library builds (which
-# wave reads which rows and columns), so its source is hashed with the kernels
+# wave reads which rows and columns) and on the compiler flags of each source
+# (the instruction scheduler), so those sources are hashed with the kernels
 COMMON_SOURCES = ["paper_2402_03074_amd/csrc/hwenou_device.hpp",
                   "paper_2402_03074_amd/csrc/hwenou_internal.hpp",
-                  "paper_2402_03074_amd/csrc/hwenou_api.hip"]
+                  "paper_2402_03074_amd/csrc/hwenou_api.hip",
+                  "paper_2402_03074_amd/build.py"]
 KERNEL_SOURCES = ["paper_2402_03074_amd/csrc/stage2d.hip"] + COMMON_SOURCES
 # rocprofv3 counter summaries (profiles/) per stage kernel and the workload
 # they were taken on
@@ -86,8 +88,12 @@ def kernel_source_hash(dim=2):
     for f in COUNTERS[dim][3]:
         with open(os.path.join(ROOT, f)) as fh:
             src = fh.read()
-        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-        src = re.sub(r"//[^\n]*", "", src)
+        if f.endswith(".py"):
+            src = re.sub(r'""".*?"""', "", src, flags=re.S)
+            src = re.sub(r"#[^\n]*", "", src)
+        else:
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            src = re.sub(r"//[^\n]*", "", src)
         h.update(re.sub(r"\s+", " ", src).strip().encode())
     return h.hexdigest()[:16]
 

@@ -24,7 +24,10 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # Per-file flags.  The 2D stage kernel runs one wave per SIMD, so nothing
 # hides its latencies but its own instruction order; LLVM's iterative ILP
 # scheduler orders it better than the default (mixed form: 4% per stage).
-SOURCE_FLAGS = {"stage2d.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
+# That scheduler fails on the 1D kernels; the max-ILP one orders them 2%
+# better than the default on a batch of 512 grids.
+SOURCE_FLAGS = {"stage2d.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+                "stage1d.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def _compile(src, verbose, extra):

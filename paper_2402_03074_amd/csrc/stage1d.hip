@@ -17,6 +17,38 @@
 
 namespace hwenou {
 
+// A read of data that no kernel writes while a stage kernel runs (the work
+// list, the instance records, the done flags, alpha and dt), through the
+// constant address space and word by word, so that at a wave-uniform address
+// it becomes a scalar load, which does not wait behind the wave's vector
+// memory traffic.
+template <class T>
+__device__ __forceinline__ T load_invariant(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "records of whole 32-bit words");
+  using Word = const __attribute__((address_space(4))) unsigned;
+  Word* q = (Word*)p;
+  unsigned v[sizeof(T) / 4];
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) v[k] = q[k];
+  T r;
+  __builtin_memcpy(&r, v, sizeof(T));
+  return r;
+}
+
+// The boundary rule of bc_index (periodic wrap, transmissive copy, mirror
+// image at a reflective wall) as selects, so that the lanes of a tile form
+// their source cells without branching on their own indices.
+__device__ __forceinline__ int source_cell(int i, int n, int bc_lo, int bc_hi, bool& mirrored) {
+  const bool lo = i < 0, out = lo || i >= n;
+  const int bc = lo ? bc_lo : bc_hi;
+  const int wrap = lo ? i + n : i - n;
+  const int mirror = lo ? -1 - i : 2 * n - 1 - i;
+  const int edge = lo ? 0 : n - 1;
+  mirrored = out && bc == BC_REFLECTIVE;
+  const int j = bc == BC_PERIODIC ? wrap : (bc == BC_REFLECTIVE ? mirror : edge);
+  return out ? j : i;
+}
+
 // Resident waves per SIMD the compiler must allow: the kernel is latency-
 // bound, and the mixed characteristic Euler kernel fits 4 waves per SIMD (128
 // registers) without spilling; the others keep the compiler's choice.
@@ -31,7 +63,12 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
     const StageArgs<TM> A) {
   constexpr int NC = EQ == EQ_EULER ? 3 : 1;
   const int lane = threadIdx.x & 63;
-  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // The wave index is uniform across the wave; saying so lets the compiler
+  // read the work list, the instance record, the done flag, alpha and dt with
+  // scalar loads (which do not wait behind the wave's vector memory traffic)
+  // instead of per-lane vector loads.
+  const int w =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (w >= A.n_waves) return;
   const SchemeParams& P = A.P;
   // Runge-Kutta combination out = ra * base + rb * (in + dt F)
@@ -39,10 +76,16 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
   constexpr double rb = ST == 0 ? 1.0 : (ST == 1 ? 0.25 : 2.0 / 3.0);
   const long long plane = A.plane;
 
-  for (int it = A.work_ptr[w]; it < A.work_ptr[w + 1]; ++it) {
-    const WorkItem wk = A.work[it];
-    if (A.done != nullptr && A.done[wk.inst]) continue;
-    const InstDev I = A.inst[wk.inst];
+  const int it_end = load_invariant(A.work_ptr + w + 1);
+  for (int it = load_invariant(A.work_ptr + w); it < it_end; ++it) {
+    const WorkItem wk = load_invariant(A.work + it);
+    // the instance's records are read together, before the done flag is
+    // tested, so that they arrive in one round trip
+    const bool done = A.done != nullptr && load_invariant(A.done + wk.inst);
+    const InstDev I = load_invariant(A.inst + wk.inst);
+    const double alpha_in = load_invariant(A.alpha + 2 * wk.inst);
+    const double dt = load_invariant(A.dt + wk.inst);
+    if (done) continue;
     const int n = I.nx;
     int i = wk.a - 1 + lane;
     // lanes past the right ring lane (i = n) take i = n + 1: the ring lane reads
@@ -50,9 +93,9 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
     if (i > n + 1) i = n + 1;
     const bool owner = lane >= 1 && lane <= kStripWidth && i < n;
     bool mir_m, mir_c, mir_p;  // mirror images at reflective walls
-    const int im = bc_index(i - 1, n, I.bc[0], I.bc[1], mir_m);
-    const int ic = bc_index(i, n, I.bc[0], I.bc[1], mir_c);
-    const int ip = bc_index(i + 1, n, I.bc[0], I.bc[1], mir_p);
+    const int im = source_cell(i - 1, n, I.bc[0], I.bc[1], mir_m);
+    const int ic = source_cell(i, n, I.bc[0], I.bc[1], mir_c);
+    const int ip = source_cell(i + 1, n, I.bc[0], I.bc[1], mir_p);
     const bool walls = EQ == EQ_EULER && (I.bc[0] == BC_REFLECTIVE || I.bc[1] == BC_REFLECTIVE);
     const double* u = A.u_in + I.offset;
     const TM* m = A.m_in + I.offset;
@@ -186,7 +229,7 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
     }
 
     // ---- fluxes: the lane on the right of x_{i-1/2} evaluates it ----
-    const TR alpha = (TR)A.alpha[2 * wk.inst];
+    const TR alpha = (TR)alpha_in;
     TR um[NC], up[NC], fl[NC], fr[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -216,7 +259,6 @@ __global__ __launch_bounds__(256, (min_waves_1d<EQ, CHAR, TR>())) void stage1d_k
     }
 
     // ---- semi-discrete RHS and RK combination ----
-    const double dt = A.dt[wk.inst];
     const double idx = 1.0 / I.dx;
     double Uo[NC];
     if (owner) {
