@@ -50,11 +50,13 @@ __device__ __forceinline__ int source_cell(int i, int n, int bc_lo, int bc_hi, b
 }
 
 // Resident waves per SIMD the compiler must allow: the kernel is latency-
-// bound, and the mixed characteristic Euler kernel fits 4 waves per SIMD (128
-// registers) without spilling; the others keep the compiler's choice.
+// bound, and the mixed characteristic Euler kernel and both component-wise
+// Euler kernels fit 4 waves per SIMD (128 registers) without spilling; the
+// FP64 characteristic kernel needs more (3 waves) and the scalar laws use far
+// fewer, so those keep the compiler's choice.
 template <int EQ, bool CHAR, class TR>
 constexpr int min_waves_1d() {
-  return (EQ == EQ_EULER && CHAR && sizeof(TR) == 4) ? 4 : 1;
+  return (EQ == EQ_EULER && (!CHAR || sizeof(TR) == 4)) ? 4 : 1;
 }
 
 // ST: the Runge-Kutta stage (0, 1, 2), compiled in like the coefficients.
