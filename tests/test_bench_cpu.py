@@ -76,3 +76,13 @@ def test_traffic_reported_only_for_current_counters(precision):
     roof, hbm = roofline()
     bench.attach_traffic(roof, hbm, rec, precision, Case, True)
     assert roof["traffic"] is None
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_committed_counters_are_those_of_the_current_sources(dim):
+    """The counter summaries under profiles/ were taken on the kernel sources,
+    the work-list builder and the per-file compiler flags as committed, so
+    that bench.py reports their HBM traffic rather than null; a change to any
+    of them must come with re-taken counters."""
+    assert "paper_2402_03074_amd/build.py" in bench.COUNTERS[dim][3]
+    assert bench.recorded_counters(dim)["source_sha256"] == bench.kernel_source_hash(dim)
