@@ -392,7 +392,7 @@ def attach_traffic(roof, hbm, rec, precision, case, fresh):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU decomposition is designed, not built)"}))
         sys.exit(2)
     import numpy as np
